@@ -1,0 +1,581 @@
+// Oracle for the compact splitting Fourier spectral method for the rotating
+// spin-orbit-coupled spin-2 Gross-Pitaevskii system (Liu, Xie, Yuan, Zhang, Zhao,
+// arXiv 2603.25282).
+//
+// TEST INFRASTRUCTURE ONLY.  This is a plain, slow, FP64 CPU implementation written
+// to be checked by eye against the paper.  Only tests/, __graft_entry__.smoke() and
+// bench.py's cpu_baseline leg may load it.  It shares no code with the HIP library.
+//
+// Conventions (paper Sec. 3.1, "Fourier spectral method" paragraph):
+//   * domain [-L, L]^d, h = 2L/N, x_j = -L + j h, N even;
+//   * forward transform carries the 1/N^d factor, inverse is unscaled;
+//   * wavenumber nu_p = pi p / L for p in [-N/2, N/2-1]; storage index k holds
+//     p = k (k < N/2) or p = k - N (k >= N/2); the Nyquist index keeps nu = -pi N/(2L).
+//   * component index i = 0..4 holds spin projection l = 2, 1, 0, -1, -2 (Sec. 1).
+//   * state layout [5][nz][ny][nx], complex128 interleaved, x fastest.
+//
+// Every floating-point value is double.  Build with -O2 -ffp-contract=off.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef std::complex<double> cd;
+static const double PI = 3.14159265358979323846264338327950288;
+static const cd I1(0.0, 1.0);
+
+struct OGrid {
+  int dim;        // 2 or 3
+  int n[3];       // nx, ny, nz (nz = 1 in 2D)
+  double L[3];    // half-widths
+};
+
+struct OParams {
+  double c0, c1, c2, Omega, gamma, gx, gy, gz;
+};
+
+static inline long npoints(const OGrid& g) {
+  return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+}
+
+// ---------------------------------------------------------------------------
+// Discrete Fourier transform (own mixed-radix implementation).
+// y[k] = sum_j x[j] exp(sign * 2 pi i j k / n).  Recursive decimation in time by
+// the smallest prime factor; a prime length falls back to the O(n^2) sum.
+// ---------------------------------------------------------------------------
+static int smallest_factor(int n) {
+  for (int r = 2; r * r <= n; ++r)
+    if (n % r == 0) return r;
+  return n;
+}
+
+// w[k] = exp(sign * 2 pi i k / ntop); at a sub-length m dividing ntop the twiddle
+// exp(sign 2 pi i t / m) is w[t * (ntop / m)].
+static void fft_rec(const cd* x, long xs, cd* y, int n, const cd* w, int ntop) {
+  if (n == 1) { y[0] = x[0]; return; }
+  int r = smallest_factor(n);
+  int m = n / r;
+  for (int s = 0; s < r; ++s) fft_rec(x + s * xs, xs * r, y + (long)s * m, m, w, ntop);
+  cd tbuf[16], ubuf[16];
+  std::vector<cd> tv, uv;
+  cd *t = tbuf, *u = ubuf;
+  if (r > 16) { tv.resize(r); uv.resize(r); t = tv.data(); u = uv.data(); }
+  long step = ntop / n;  // twiddle index stride for length n
+  for (int k = 0; k < m; ++k) {
+    for (int s = 0; s < r; ++s) t[s] = y[(long)s * m + k] * w[((long)s * k * step) % ntop];
+    for (int q = 0; q < r; ++q) {
+      cd acc = 0.0;
+      for (int s = 0; s < r; ++s) acc += t[s] * w[((long)s * q * m * step) % ntop];
+      u[q] = acc;
+    }
+    for (int q = 0; q < r; ++q) y[k + (long)q * m] = u[q];
+  }
+}
+
+static std::vector<cd> twiddles(int n, int sign) {
+  std::vector<cd> w(n);
+  for (int k = 0; k < n; ++k) {
+    double a = sign * 2.0 * PI * (double)k / (double)n;
+    w[k] = cd(std::cos(a), std::sin(a));
+  }
+  return w;
+}
+
+// Transform every line of `data` along axis `ax`.  sign=-1 forward (scaled by 1/n),
+// sign=+1 inverse (unscaled).
+static void fft_axis(const OGrid& g, cd* data, int ax, int sign) {
+  int nx = g.n[0], ny = g.n[1], nz = (g.dim == 3 ? g.n[2] : 1);
+  int n = g.n[ax];
+  long stride = (ax == 0) ? 1 : (ax == 1 ? nx : (long)nx * ny);
+  long nlines = (long)nx * ny * nz / n;
+  std::vector<cd> w = twiddles(n, sign);
+  double scale = (sign < 0) ? 1.0 / (double)n : 1.0;
+#pragma omp parallel
+  {
+    std::vector<cd> in(n), out(n);
+#pragma omp for schedule(static)
+    for (long line = 0; line < nlines; ++line) {
+      long base;
+      if (ax == 0) base = line * nx;
+      else if (ax == 1) base = (line / nx) * (long)nx * ny + (line % nx);
+      else base = line;  // ax == 2: line enumerates (y, x) in one z-slab
+      for (int j = 0; j < n; ++j) in[j] = data[base + j * stride];
+      fft_rec(in.data(), 1, out.data(), n, w.data(), n);
+      for (int j = 0; j < n; ++j) data[base + j * stride] = out[j] * scale;
+    }
+  }
+}
+
+// d-dimensional transform of one scalar field.
+static void fft_nd(const OGrid& g, cd* data, int sign) {
+  for (int ax = 0; ax < g.dim; ++ax) fft_axis(g, data, ax, sign);
+}
+
+static inline double wavenumber(int k, int n, double L) {
+  int p = (k < n / 2) ? k : k - n;
+  return PI * (double)p / L;
+}
+
+// ---------------------------------------------------------------------------
+// Exact linear propagator exp(i delta Q) for one wavevector, Sec. 3.1: Q has
+// diagonal -Omega (2, 1, 0, -1, -2) and off-diagonals gamma a (1, sqrt6/2, sqrt6/2, 1)
+// above, gamma conj(a) below, with a = -nu_q - i nu_p.  Entry (i, j) of exp(i tau Q)
+// is a^(j-i) c_ij for j >= i and conj(a)^(i-j) c_ji for i > j, with the fifteen c_ij
+// written out in the paper.  eta1 = cos(2 lam tau) - 1 and eta2 = cos(lam tau) - 1
+// are evaluated as -2 sin^2(lam tau) and -2 sin^2(lam tau / 2) (same value, no
+// cancellation).  lam = 0 (Omega = 0 and nu_perp = 0) gives the identity.
+// out is row-major 5x5.
+// ---------------------------------------------------------------------------
+static void propagator(double Omega, double gamma, double nu_p, double nu_q,
+                       double tau, cd* out) {
+  cd a(-nu_q, -nu_p);
+  double xi = gamma * std::abs(a);
+  double lam = std::sqrt(Omega * Omega + xi * xi);
+  for (int i = 0; i < 25; ++i) out[i] = 0.0;
+  if (lam == 0.0) {
+    for (int i = 0; i < 5; ++i) out[i * 5 + i] = 1.0;
+    return;
+  }
+  double s1 = std::sin(lam * tau), s2 = std::sin(0.5 * lam * tau);
+  cd eta1 = -2.0 * s1 * s1;
+  cd eta2 = -2.0 * s2 * s2;
+  cd eta3 = I1 * std::sin(2.0 * lam * tau);
+  cd eta4 = I1 * s1;
+  double O = Omega, O2 = O * O, O3 = O2 * O, O4 = O2 * O2;
+  double x2 = xi * xi, x4 = x2 * x2;
+  double l2 = lam * lam, l3 = l2 * lam, l4 = l2 * l2;
+  double g = gamma, g2 = g * g, g3 = g2 * g, g4 = g2 * g2;
+  double r6 = std::sqrt(6.0);
+
+  cd c11 = (1.0 / (8.0 * l4)) * ((8.0 * O4 + 8.0 * O2 * x2 + x4) * eta1 + 4.0 * x2 * (2.0 * O2 + x2) * eta2
+                                 - 4.0 * O * lam * (2.0 * O2 + x2) * eta3 - 8.0 * O * lam * x2 * eta4 + 8.0 * l4);
+  cd c12 = (g / (4.0 * l4)) * (-O * (4.0 * O2 + 3.0 * x2) * eta1 + 4.0 * O3 * eta2 + lam * (4.0 * O2 + x2) * eta3
+                               - 2.0 * lam * (2.0 * O2 - x2) * eta4);
+  cd c13 = (r6 * g2 / (4.0 * l4)) * ((2.0 * O2 + x2) * eta2 - 2.0 * O * lam * eta4 + 2.0 * l2) * eta2;
+  cd c14 = (g3 / (2.0 * l4)) * (-O * eta2 + lam * eta4) * eta2;
+  cd c15 = (g4 / (8.0 * l4)) * (eta1 - 4.0 * eta2);
+  cd c22 = (1.0 / (2.0 * l4)) * (2.0 * x2 * eta2 + l2) * ((2.0 * O2 + x2) * eta2 - 2.0 * O * lam * eta4 + 2.0 * l2);
+  cd c23 = (r6 * g / (2.0 * l4)) * (x2 * eta2 + l2) * (-O * eta2 + lam * eta4);
+  cd c24 = (g2 / (2.0 * l4)) * (2.0 * x2 * eta2 + 3.0 * l2) * eta2;
+  cd c25 = c14 + (O * g3 / l4) * eta2 * eta2;
+  cd c33 = (3.0 * x2 / (4.0 * l4)) * (x2 * eta1 + 4.0 * O2 * eta2) + 1.0;
+  cd c34 = c23 + (r6 * O * g / l4) * (x2 * eta2 + l2) * eta2;
+  cd c35 = c13 + (r6 * O * g2 / l3) * eta2 * eta4;
+  cd c44 = c22 + (2.0 * O / l3) * (2.0 * x2 * eta2 + l2) * eta4;
+  cd c45 = c12 + (O * g / (2.0 * l4)) * ((4.0 * O2 + 3.0 * x2) * eta1 - 4.0 * O2 * eta2);
+  cd c55 = c11 + (O / l3) * ((2.0 * O2 + x2) * eta3 + 2.0 * x2 * eta4);
+
+  cd c[5][5];
+  c[0][0] = c11; c[0][1] = c12; c[0][2] = c13; c[0][3] = c14; c[0][4] = c15;
+  c[1][1] = c22; c[1][2] = c23; c[1][3] = c24; c[1][4] = c25;
+  c[2][2] = c33; c[2][3] = c34; c[2][4] = c35;
+  c[3][3] = c44; c[3][4] = c45;
+  c[4][4] = c55;
+  cd apow[5], abpow[5];
+  apow[0] = abpow[0] = 1.0;
+  for (int k = 1; k < 5; ++k) { apow[k] = apow[k - 1] * a; abpow[k] = abpow[k - 1] * std::conj(a); }
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j)
+      out[i * 5 + j] = (j >= i) ? apow[j - i] * c[i][j] : abpow[i - j] * c[j][i];
+}
+
+// ---------------------------------------------------------------------------
+// Linear substep: Phi <- IFFT[ exp(-i delta |nu|^2/2) exp(i delta Q) FFT[Phi] ]
+// (Sec. 3.1, solution of the Fourier-space ODE, eq. (sl1)); in 3D, Q depends on
+// (nu_p, nu_q) only and |nu|^2 includes nu_r (3D remark of Sec. 3.1).
+// ---------------------------------------------------------------------------
+static void linear_step(const OGrid& g, const OParams& P, double delta, cd* psi) {
+  long np = npoints(g);
+  for (int c = 0; c < 5; ++c) fft_nd(g, psi + c * np, -1);
+  int nx = g.n[0], ny = g.n[1], nz = (g.dim == 3 ? g.n[2] : 1);
+#pragma omp parallel for schedule(static)
+  for (long pq = 0; pq < (long)nx * ny; ++pq) {
+    int kx = (int)(pq % nx), ky = (int)(pq / nx);
+    double nup = wavenumber(kx, nx, g.L[0]);
+    double nuq = wavenumber(ky, ny, g.L[1]);
+    cd E[25];
+    propagator(P.Omega, P.gamma, nup, nuq, delta, E);
+    for (int kz = 0; kz < nz; ++kz) {
+      double nur = (g.dim == 3) ? wavenumber(kz, nz, g.L[2]) : 0.0;
+      double k2 = nup * nup + nuq * nuq + nur * nur;
+      cd kin = std::exp(cd(0.0, -0.5 * delta * k2));
+      long idx = (long)kz * nx * ny + pq;
+      cd v[5], w[5];
+      for (int i = 0; i < 5; ++i) v[i] = psi[i * np + idx];
+      for (int i = 0; i < 5; ++i) {
+        cd acc = 0.0;
+        for (int j = 0; j < 5; ++j) acc += E[i * 5 + j] * v[j];
+        w[i] = kin * acc;
+      }
+      for (int i = 0; i < 5; ++i) psi[i * np + idx] = w[i];
+    }
+  }
+  for (int c = 0; c < 5; ++c) fft_nd(g, psi + c * np, +1);
+}
+
+// ---------------------------------------------------------------------------
+// Nonlinear substep at one grid point, Sec. 3.2, eq. (solution2):
+//   Psi(t) = exp(-i d [V + (c0 + c2/5) rho]) exp(-i c1 d F.f)
+//            [cos(c2 S d) Psi + (i/S) sin(c2 S d) (rho/5 Psi - A00 A conj(Psi))]
+// with S = sqrt((rho/5)^2 - |A00|^2/5) and exp(-i c1 d F.f) from the spin-2
+// polynomial in N = F.f/|F|, kappa = c1 |F| d.
+// Limits the paper leaves implicit: S = 0 uses sin(c2 S d)/S = c2 d; |F| = 0 makes
+// the spin rotation the identity; S^2 < 0 from rounding is clamped to 0.
+// ---------------------------------------------------------------------------
+static void ff_matrix(double Fx, double Fy, double Fz, cd* M) {
+  // F.f (Sec. 1): diagonal F_z (2,1,0,-1,-2); F_- above, F_+ below with the
+  // sqrt6/2 weights on the middle links.
+  cd Fp(Fx, Fy), Fm(Fx, -Fy);
+  double h6 = std::sqrt(6.0) / 2.0;
+  for (int i = 0; i < 25; ++i) M[i] = 0.0;
+  M[0 * 5 + 0] = 2.0 * Fz; M[1 * 5 + 1] = Fz; M[2 * 5 + 2] = 0.0; M[3 * 5 + 3] = -Fz; M[4 * 5 + 4] = -2.0 * Fz;
+  M[0 * 5 + 1] = Fm;      M[1 * 5 + 0] = Fp;
+  M[1 * 5 + 2] = h6 * Fm; M[2 * 5 + 1] = h6 * Fp;
+  M[2 * 5 + 3] = h6 * Fm; M[3 * 5 + 2] = h6 * Fp;
+  M[3 * 5 + 4] = Fm;      M[4 * 5 + 3] = Fp;
+}
+
+static void matmul5(const cd* A, const cd* B, cd* C) {
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      cd acc = 0.0;
+      for (int k = 0; k < 5; ++k) acc += A[i * 5 + k] * B[k * 5 + j];
+      C[i * 5 + j] = acc;
+    }
+}
+
+struct Densities { double rho, Fx, Fy, Fz; cd A00; };
+
+static Densities densities(const cd* psi) {
+  // Sec. 1: rho = sum |psi_l|^2, F_x, F_y, F_z, A00 = (2 psi2 psi-2 - 2 psi1 psi-1 + psi0^2)/sqrt5.
+  const cd &p2 = psi[0], &p1 = psi[1], &p0 = psi[2], &m1 = psi[3], &m2 = psi[4];
+  double h6 = std::sqrt(6.0) / 2.0;
+  Densities d;
+  d.rho = std::norm(p2) + std::norm(p1) + std::norm(p0) + std::norm(m1) + std::norm(m2);
+  cd fx = std::conj(p1) * p2 + std::conj(p2) * p1 + std::conj(m2) * m1 + std::conj(m1) * m2
+          + h6 * (std::conj(p0) * p1 + std::conj(p1) * p0 + std::conj(m1) * p0 + std::conj(p0) * m1);
+  cd fy = I1 * (std::conj(p1) * p2 - std::conj(p2) * p1 + std::conj(m2) * m1 - std::conj(m1) * m2
+                + h6 * (std::conj(p0) * p1 - std::conj(p1) * p0 + std::conj(m1) * p0 - std::conj(p0) * m1));
+  d.Fx = fx.real();
+  d.Fy = fy.real();
+  d.Fz = 2.0 * std::norm(p2) + std::norm(p1) - std::norm(m1) - 2.0 * std::norm(m2);
+  d.A00 = (2.0 * p2 * m2 - 2.0 * p1 * m1 + p0 * p0) / std::sqrt(5.0);
+  return d;
+}
+
+static void nl_point(const OParams& P, double V, double delta, cd* psi) {
+  Densities d = densities(psi);
+  double S2 = (d.rho / 5.0) * (d.rho / 5.0) - std::norm(d.A00) / 5.0;
+  if (S2 < 0.0) S2 = 0.0;
+  double S = std::sqrt(S2);
+  double cs = std::cos(P.c2 * S * delta);
+  double sn_over_S = (S == 0.0) ? P.c2 * delta : std::sin(P.c2 * S * delta) / S;
+  // (A conj Psi)_i = (-1)^(i-1) conj(psi_{6-i}) / sqrt5 with 1-based i (Sec. 1).
+  double r5 = 1.0 / std::sqrt(5.0);
+  cd Apsib[5] = { r5 * std::conj(psi[4]), -r5 * std::conj(psi[3]), r5 * std::conj(psi[2]),
+                  -r5 * std::conj(psi[1]), r5 * std::conj(psi[0]) };
+  cd b[5];
+  for (int i = 0; i < 5; ++i)
+    b[i] = cs * psi[i] + I1 * sn_over_S * ((d.rho / 5.0) * psi[i] - d.A00 * Apsib[i]);
+
+  // exp(-i c1 d F.f) = I + i g1 N + g2 N^2 + i g3 N^3 + g4 N^4, N = F.f/|F|.
+  double Fabs = std::sqrt(d.Fx * d.Fx + d.Fy * d.Fy + d.Fz * d.Fz);
+  cd R[25];
+  for (int i = 0; i < 25; ++i) R[i] = 0.0;
+  for (int i = 0; i < 5; ++i) R[i * 5 + i] = 1.0;
+  if (Fabs > 0.0) {
+    double kap = P.c1 * Fabs * delta;
+    double g1 = std::sin(2.0 * kap) / 6.0 - 4.0 / 3.0 * std::sin(kap);
+    double g2 = 4.0 / 3.0 * std::cos(kap) - std::cos(2.0 * kap) / 12.0 - 5.0 / 4.0;
+    double g3 = std::sin(kap) / 3.0 - std::sin(2.0 * kap) / 6.0;
+    double g4 = std::cos(2.0 * kap) / 12.0 - std::cos(kap) / 3.0 + 0.25;
+    cd N1[25], N2[25], N3[25], N4[25];
+    ff_matrix(d.Fx / Fabs, d.Fy / Fabs, d.Fz / Fabs, N1);
+    matmul5(N1, N1, N2);
+    matmul5(N2, N1, N3);
+    matmul5(N3, N1, N4);
+    for (int i = 0; i < 25; ++i)
+      R[i] += I1 * g1 * N1[i] + g2 * N2[i] + I1 * g3 * N3[i] + g4 * N4[i];
+  }
+  cd ph = std::exp(cd(0.0, -delta * (V + (P.c0 + P.c2 / 5.0) * d.rho)));
+  for (int i = 0; i < 5; ++i) {
+    cd acc = 0.0;
+    for (int j = 0; j < 5; ++j) acc += R[i * 5 + j] * b[j];
+    psi[i] = ph * acc;
+  }
+}
+
+// Trap of eq. (harmonic) evaluated at the rotated point R(theta) x, with
+// R(theta) = [[cos, sin], [-sin, cos]] acting on (x, y) (Sec. 3.1, mapping).
+static inline double trap_rotated(const OParams& P, double theta, double x, double y, double z) {
+  double c = std::cos(theta), s = std::sin(theta);
+  double X = c * x + s * y, Y = -s * x + c * y;
+  return 0.5 * (P.gx * P.gx * X * X + P.gy * P.gy * Y * Y + P.gz * P.gz * z * z);
+}
+
+static inline double coord(const OGrid& g, int ax, int j) {
+  double h = 2.0 * g.L[ax] / (double)g.n[ax];
+  return -g.L[ax] + (double)j * h;
+}
+
+// Nonlinear substep over the grid with the trap rotated by theta (theta = 0: lab frame).
+static void nl_step(const OGrid& g, const OParams& P, double delta, double theta, cd* psi) {
+  long np = npoints(g);
+  int nx = g.n[0], ny = g.n[1];
+#pragma omp parallel for schedule(static)
+  for (long idx = 0; idx < np; ++idx) {
+    int ix = (int)(idx % nx), iy = (int)((idx / nx) % ny), iz = (int)(idx / ((long)nx * ny));
+    double z = (g.dim == 3) ? coord(g, 2, iz) : 0.0;
+    double V = trap_rotated(P, theta, coord(g, 0, ix), coord(g, 1, iy), z);
+    cd v[5];
+    for (int i = 0; i < 5; ++i) v[i] = psi[i * np + idx];
+    nl_point(P, V, delta, v);
+    for (int i = 0; i < 5; ++i) psi[i * np + idx] = v[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rotation mapping by RSDA (Sec. 3.1, eqs. (RSDA1)/(RSDA2)): three shears
+// exp(a y d_x) exp(b x d_y) exp(a y d_x), each a 1D transform, a phase
+// exp(i nu a y) per Fourier mode, and the inverse transform.
+// ---------------------------------------------------------------------------
+static void shear(const OGrid& g, cd* f, int ax, double a) {
+  // ax = 0: f(x, y) <- f(x + a y, y);  ax = 1: f(x, y) <- f(x, y + a x).
+  int nx = g.n[0], ny = g.n[1], nz = (g.dim == 3 ? g.n[2] : 1);
+  fft_axis(g, f, ax, -1);
+  int other = 1 - ax;
+#pragma omp parallel for schedule(static)
+  for (long idx = 0; idx < (long)nx * ny * nz; ++idx) {
+    int ix = (int)(idx % nx), iy = (int)((idx / nx) % ny);
+    int kk = (ax == 0) ? ix : iy;
+    int jo = (ax == 0) ? iy : ix;
+    double nu = wavenumber(kk, g.n[ax], g.L[ax]);
+    double w = coord(g, other, jo);
+    f[idx] *= std::exp(cd(0.0, nu * a * w));
+  }
+  fft_axis(g, f, ax, +1);
+}
+
+// forward = true: Phi = M_t Psi, phi_l = exp(-i l Omega t) psi_l(R(t) x)  (RSDA1)
+// forward = false: Psi = M_t^{-1} Phi, psi_l = exp(i l Omega t) phi_l(R(t)^{-1} x) (RSDA2)
+static void rotation_map(const OGrid& g, const OParams& P, double t, bool forward, cd* psi) {
+  long np = npoints(g);
+  double th = P.Omega * t;
+  double a = forward ? std::tan(th / 2.0) : -std::tan(th / 2.0);
+  double b = forward ? -std::sin(th) : std::sin(th);
+  static const int ell[5] = {2, 1, 0, -1, -2};
+  for (int c = 0; c < 5; ++c) {
+    cd* f = psi + c * np;
+    shear(g, f, 0, a);
+    shear(g, f, 1, b);
+    shear(g, f, 0, a);
+    cd ph = std::exp(cd(0.0, (forward ? -1.0 : 1.0) * ell[c] * P.Omega * t));
+    for (long i = 0; i < np; ++i) f[i] *= ph;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time composition, Sec. 3.3.  The coefficients a_j multiply the nonlinear flow
+// and b_j the linear flow (the reading under which Algorithm 1 -- nonlinear half
+// steps outside -- and Table Acc1 agree):
+//   TS2: N(tau/2) L(tau) N(tau/2)
+//   TS4: N(a1) L(b1) N(a2) L(b2) N(a2) L(b1) N(a1) (times tau), with
+//        a1 = 1/(2(2-2^(1/3))), a2 = (1-2^(1/3))/(2(2-2^(1/3))),
+//        b1 = 1/(2-2^(1/3)),    b2 = -2^(1/3)/(2-2^(1/3)).
+// Rotating frame (mode 0): the state is Phi; the nonlinear substep uses the trap at
+// R(Omega s) x with s the clock advanced by the linear substeps only.
+// Lab frame (mode 1): Algorithm 1 literally, the mapping M_s before and M_{s+d}^{-1}
+// after every linear substep, the nonlinear substep with the lab trap.
+// ---------------------------------------------------------------------------
+struct Scheme { int m; double a[4]; double b[4]; };
+
+static Scheme make_scheme(int order) {
+  Scheme sc;
+  if (order == 2) {
+    sc.m = 2; sc.a[0] = 0.5; sc.a[1] = 0.5; sc.b[0] = 1.0; sc.b[1] = 0.0;
+  } else {
+    double c = std::cbrt(2.0);
+    double den = 2.0 - c;
+    sc.m = 4;
+    sc.a[0] = sc.a[3] = 1.0 / (2.0 * den);
+    sc.a[1] = sc.a[2] = (1.0 - c) / (2.0 * den);
+    sc.b[0] = sc.b[2] = 1.0 / den;
+    sc.b[1] = -c / den;
+    sc.b[3] = 0.0;
+  }
+  return sc;
+}
+
+static void evolve(const OGrid& g, const OParams& P, int order, double tau, long nsteps,
+                   double t0, int mode, cd* psi) {
+  Scheme sc = make_scheme(order);
+  double t = t0;
+  for (long n = 0; n < nsteps; ++n) {
+    double s = t;
+    for (int j = 0; j < sc.m; ++j) {
+      if (sc.a[j] != 0.0) nl_step(g, P, sc.a[j] * tau, mode == 0 ? P.Omega * s : 0.0, psi);
+      if (sc.b[j] != 0.0) {
+        double d = sc.b[j] * tau;
+        if (mode == 0) {
+          linear_step(g, P, d, psi);
+        } else {
+          rotation_map(g, P, s, true, psi);
+          linear_step(g, P, d, psi);
+          rotation_map(g, P, s + d, false, psi);
+        }
+        s += d;
+      }
+    }
+    t = t0 + (double)(n + 1) * tau;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Observables, Sec. 2, on the discrete l2 inner product of Sec. 3.4 (h^d sum):
+//   mass N, energy E, magnetization M, angular momentum <Lz>.
+// Derivatives are spectral (Sec. 3.1).  theta rotates the trap (rotating frame).
+// ---------------------------------------------------------------------------
+static void spectral_derivative(const OGrid& g, const cd* f, int ax, cd* out) {
+  long np = npoints(g);
+  int nx = g.n[0], ny = g.n[1];
+  std::memcpy((void*)out, (const void*)f, sizeof(cd) * np);
+  fft_nd(g, out, -1);
+  for (long idx = 0; idx < np; ++idx) {
+    int k = (ax == 0) ? (int)(idx % nx) : (ax == 1 ? (int)((idx / nx) % ny) : (int)(idx / ((long)nx * ny)));
+    out[idx] *= cd(0.0, wavenumber(k, g.n[ax], g.L[ax]));
+  }
+  fft_nd(g, out, +1);
+}
+
+static void observables(const OGrid& g, const OParams& P, double theta, const cd* psi, double* out) {
+  long np = npoints(g);
+  int nx = g.n[0], ny = g.n[1];
+  double hd = 1.0;
+  for (int ax = 0; ax < g.dim; ++ax) hd *= 2.0 * g.L[ax] / (double)g.n[ax];
+  int nd = g.dim;
+  std::vector<cd> D((size_t)5 * nd * np);  // D[(c*nd + ax)*np + idx] = d_ax psi_c
+  for (int c = 0; c < 5; ++c)
+    for (int ax = 0; ax < nd; ++ax) spectral_derivative(g, psi + c * np, ax, D.data() + ((long)c * nd + ax) * np);
+  static const double ell[5] = {2, 1, 0, -1, -2};
+  double h6 = std::sqrt(6.0) / 2.0;
+  double mass = 0, magn = 0, lz = 0, ekin = 0, epot = 0, eint = 0;
+  cd esoc = 0.0;
+  for (long idx = 0; idx < np; ++idx) {
+    int ix = (int)(idx % nx), iy = (int)((idx / nx) % ny), iz = (int)(idx / ((long)nx * ny));
+    double x = coord(g, 0, ix), y = coord(g, 1, iy), z = (nd == 3) ? coord(g, 2, iz) : 0.0;
+    double V = trap_rotated(P, theta, x, y, z);
+    cd v[5], dx[5], dy[5];
+    for (int c = 0; c < 5; ++c) {
+      v[c] = psi[c * np + idx];
+      dx[c] = D[((long)c * nd + 0) * np + idx];
+      dy[c] = D[((long)c * nd + 1) * np + idx];
+      double grad2 = 0.0;
+      for (int ax = 0; ax < nd; ++ax) grad2 += std::norm(D[((long)c * nd + ax) * np + idx]);
+      ekin += 0.5 * grad2;
+      mass += std::norm(v[c]);
+      magn += ell[c] * std::norm(v[c]);
+      epot += V * std::norm(v[c]);
+      // Lz psi = -i (x d_y - y d_x) psi
+      cd Lz = -I1 * (x * dy[c] - y * dx[c]);
+      lz += (std::conj(v[c]) * Lz).real();
+    }
+    Densities d = densities(v);
+    eint += 0.5 * P.c0 * d.rho * d.rho + 0.5 * P.c1 * (d.Fx * d.Fx + d.Fy * d.Fy + d.Fz * d.Fz)
+            + 0.5 * P.c2 * std::norm(d.A00);
+    // SOC: L+- = i d_y +- d_x; Psi^H S Psi with S of Sec. 1.
+    cd Lp[5], Lm[5];
+    for (int c = 0; c < 5; ++c) { Lp[c] = I1 * dy[c] + dx[c]; Lm[c] = I1 * dy[c] - dx[c]; }
+    cd sps = std::conj(v[0]) * Lm[1]
+             + std::conj(v[1]) * (Lp[0] + h6 * Lm[2])
+             + std::conj(v[2]) * (h6 * Lp[1] + h6 * Lm[3])
+             + std::conj(v[3]) * (h6 * Lp[2] + Lm[4])
+             + std::conj(v[4]) * Lp[3];
+    esoc += sps;
+  }
+  out[0] = hd * mass;
+  out[1] = hd * (ekin + epot + eint - P.gamma * esoc.real()) - P.Omega * hd * lz;
+  out[2] = hd * magn;
+  out[3] = hd * lz;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI for the Python test harness.
+// ---------------------------------------------------------------------------
+static OGrid mkgrid(int dim, const int* n, const double* L) {
+  OGrid g;
+  g.dim = dim;
+  for (int i = 0; i < 3; ++i) { g.n[i] = (i < dim) ? n[i] : 1; g.L[i] = (i < dim) ? L[i] : 1.0; }
+  return g;
+}
+static OParams mkparams(const double* p) {
+  OParams P;
+  P.c0 = p[0]; P.c1 = p[1]; P.c2 = p[2]; P.Omega = p[3]; P.gamma = p[4];
+  P.gx = p[5]; P.gy = p[6]; P.gz = p[7];
+  return P;
+}
+
+extern "C" {
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// One d-dimensional transform of a single scalar field in place; sign -1 forward
+// (scaled by 1/N^d), +1 inverse (unscaled).
+void orc_fft(int dim, const int* n, double* data, int sign) {
+  double L[3] = {1, 1, 1};
+  OGrid g = mkgrid(dim, n, L);
+  fft_nd(g, reinterpret_cast<cd*>(data), sign);
+}
+
+void orc_propagator(double Omega, double gamma, double nu_p, double nu_q, double delta, double* out25) {
+  propagator(Omega, gamma, nu_p, nu_q, delta, reinterpret_cast<cd*>(out25));
+}
+
+void orc_nl_point(const double* params, double V, double delta, double* psi5) {
+  OParams P = mkparams(params);
+  nl_point(P, V, delta, reinterpret_cast<cd*>(psi5));
+}
+
+void orc_linear_step(int dim, const int* n, const double* L, const double* params, double delta, double* psi) {
+  linear_step(mkgrid(dim, n, L), mkparams(params), delta, reinterpret_cast<cd*>(psi));
+}
+
+void orc_nl_step(int dim, const int* n, const double* L, const double* params, double delta, double theta,
+                 double* psi) {
+  nl_step(mkgrid(dim, n, L), mkparams(params), delta, theta, reinterpret_cast<cd*>(psi));
+}
+
+void orc_rotation_map(int dim, const int* n, const double* L, const double* params, double t, int forward,
+                      double* psi) {
+  rotation_map(mkgrid(dim, n, L), mkparams(params), t, forward != 0, reinterpret_cast<cd*>(psi));
+}
+
+void orc_evolve(int dim, const int* n, const double* L, const double* params, int order, double tau, long nsteps,
+                double t0, int mode, double* psi) {
+  evolve(mkgrid(dim, n, L), mkparams(params), order, tau, nsteps, t0, mode, reinterpret_cast<cd*>(psi));
+}
+
+void orc_observables(int dim, const int* n, const double* L, const double* params, double theta, const double* psi,
+                     double* out4) {
+  observables(mkgrid(dim, n, L), mkparams(params), theta, reinterpret_cast<const cd*>(psi), out4);
+}
+
+}  // extern "C"
