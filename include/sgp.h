@@ -1,0 +1,128 @@
+/*
+ * sgp.h -- C ABI of the MI355X (gfx950) split-step library for the rotating
+ * spin-orbit-coupled spin-2 Gross-Pitaevskii system, following the compact
+ * splitting Fourier spectral method of Liu, Xie, Yuan, Zhang and Zhao
+ * (arXiv 2603.25282).
+ *
+ * The model (Sec. 1, eq. CGPEs): i d_t Psi = (H0 I5 + c1 F.f - gamma S) Psi
+ *   + c2 A00 A conj(Psi), H0 = -Laplace/2 + V + c0 rho - Omega Lz, with the harmonic
+ * trap V = (gx^2 x^2 + gy^2 y^2 [+ gz^2 z^2])/2 (eq. harmonic).
+ *
+ * Frame.  The library evolves the rotating-frame state Phi of the function-rotation
+ * mapping with a phase factor (Sec. 3.1, eq. mapping): phi_l(x, t) =
+ * exp(-i l Omega t) psi_l(R(t) x, t).  At t = 0, Phi equals the lab-frame Psi.  The
+ * linear flow of Phi is time independent (eq. linearEQ2) and is integrated exactly
+ * per wavevector (eq. sl1); the nonlinear flow (eq. solution2) sees the trap at the
+ * rotated point R(Omega s) x, s being the clock advanced by the linear substeps.
+ *
+ * Discretisation (Sec. 3.1): domain [-L, L]^d with periodic boundary conditions,
+ * N points per axis, h = 2L/N, x_j = -L + j h; wavenumbers nu_p = pi p / L,
+ * p in [-N/2, N/2 - 1] (the Nyquist mode keeps nu = -pi N/(2L)).
+ *
+ * State layout (device memory, owned by the caller): [5][nz][ny][nx] complex,
+ * interleaved (re, im), x fastest; component i = 0..4 holds spin projection
+ * l = 2, 1, 0, -1, -2.  Element type: complex64 (SGP_C64) or complex128 (SGP_C128).
+ *
+ * Memory: the library allocates no device memory.  The caller asks for
+ * sgp_workspace_size() bytes, allocates them (e.g. a torch tensor), and hands them
+ * over with sgp_set_workspace(); the workspace holds FFT twiddles, propagator
+ * tables, the device clock and reduction partials, and must stay valid until
+ * sgp_destroy() or the next sgp_set_workspace().
+ *
+ * Streams: every device operation is enqueued on the stream given to
+ * sgp_create() (a hipStream_t, or NULL for the default stream).  sgp_step() does
+ * not synchronise; sgp_observables() and setup calls do.
+ *
+ * Errors: every int-returning call returns SGP_OK (0) or a negative SGP_ERR_*
+ * code; sgp_last_error() gives a message.  No C++ exception crosses this ABI.
+ * A context is not thread safe; use one context per stream.
+ */
+#ifndef SGP_H
+#define SGP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SGP_OK = 0,
+  SGP_ERR_ARG = -1,         /* bad argument (null pointer, unsupported size, ...) */
+  SGP_ERR_STATE = -2,       /* call out of order (no workspace, no propagator)     */
+  SGP_ERR_HIP = -3,         /* a HIP runtime call failed                           */
+  SGP_ERR_NONFINITE = -4,   /* a non-finite value was found                        */
+  SGP_ERR_WORKSPACE = -5    /* workspace too small                                 */
+};
+
+enum { SGP_C64 = 0, SGP_C128 = 1 };  /* element type of the state */
+enum { SGP_TS2 = 2, SGP_TS4 = 4 };   /* time composition (Sec. 3.3) */
+
+typedef struct sgp_ctx sgp_ctx;
+
+/* Grid: dim = 2 or 3; n[0..dim-1] = points along x, y[, z]; L[] = half-widths.
+ * Supported n per axis: 16, 32, 64, 128, 256, 512 (and 384 along x/y in 2D). */
+typedef struct {
+  int dim;
+  int n[3];
+  double L[3];
+} sgp_grid;
+
+/* Physics (Sec. 1): interaction constants c0 (density), c1 (spin exchange),
+ * c2 (singlet pairing); rotation speed Omega (about z); SOC strength gamma; trap
+ * frequencies gx, gy, gz (gz unused in 2D). */
+typedef struct {
+  double c0, c1, c2, Omega, gamma, gx, gy, gz;
+} sgp_params;
+
+/* Create a context for one grid, parameter set and element type.  hip_stream is a
+ * hipStream_t (NULL = default stream).  On success *out receives the context. */
+int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* hip_stream, sgp_ctx** out);
+
+/* Bytes of device workspace the context needs. */
+int sgp_workspace_size(const sgp_ctx* ctx, size_t* bytes);
+
+/* Hand over caller-owned device memory of at least sgp_workspace_size() bytes
+ * (256-byte aligned).  Uploads the FFT twiddle tables (synchronous). */
+int sgp_set_workspace(sgp_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Build, in FP64 on the device, the exact linear propagator
+ * exp(-i d |nu|^2 / 2) exp(i d Q) (Sec. 3.1, eq. sl1 and the closed form of
+ * exp(i tau Q), precomputed once as in Remark comput-cost) for every distinct linear
+ * substep d of the scheme: TS2 {tau}, TS4 {b1 tau, b2 tau}.  The tables are stored
+ * rounded to the state's precision.  tau may be negative (backward evolution).
+ * Synchronous. */
+int sgp_build_propagator(sgp_ctx* ctx, double tau, int scheme);
+
+/* Advance the state in place by nsteps steps of the scheme built by
+ * sgp_build_propagator(), from the context clock t to t + nsteps * tau (Sec. 3.3):
+ *   TS2: N(tau/2) L(tau) N(tau/2)
+ *   TS4: N(a1) L(b1) N(a2) L(b2) N(a2) L(b1) N(a1)   (times tau)
+ * with N the exact nonlinear flow and L the exact linear flow.  Adjacent
+ * nonlinear substeps of consecutive steps are merged (same clock value).
+ * psi_dev: device pointer to the state (layout above), physical space on entry and
+ * exit.  Asynchronous on the context stream; nsteps = 0 is a no-op. */
+int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
+
+/* Observables of the state at the current clock (Sec. 2, discrete h^d sums):
+ * out[0] mass N, out[1] energy E, out[2] magnetization M, out[3] <Lz>.  Spatial
+ * derivatives are spectral; the trap is taken at the rotated point R(Omega t) x.
+ * FP64 accumulation.  Synchronous. */
+int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
+
+/* Rotation clock t (the time of the rotating frame the state lives in). */
+int sgp_get_time(const sgp_ctx* ctx, double* t);
+int sgp_set_time(sgp_ctx* ctx, double t);
+
+/* Release the context (not the caller's workspace or state). */
+void sgp_destroy(sgp_ctx* ctx);
+
+/* Message of the last error on this context ("" if none); ctx may be NULL for
+ * errors raised by sgp_create(). */
+const char* sgp_last_error(const sgp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGP_H */

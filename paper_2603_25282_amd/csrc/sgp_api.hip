@@ -1,0 +1,411 @@
+// Host side of the C ABI declared in include/sgp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sgp.h"
+#include "sgp_device.hpp"
+#include "sgp_kernels.hpp"
+
+using namespace sgp;
+
+namespace {
+
+const double kPi = 3.14159265358979323846264338327950288;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <int... Rs>
+std::vector<int> radix_list(RadixList<Rs...>) { return {Rs...}; }
+
+template <int N, int E>
+std::vector<int> plan_of(bool fwd) {
+  return fwd ? radix_list(typename Plan<N, E>::fwd{}) : radix_list(typename Plan<N, E>::inv{});
+}
+
+bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
+
+std::vector<int> plan_radices(int n, bool fwd) {
+  switch (n) {
+    case 16: return plan_of<16, 8>(fwd);
+    case 32: return plan_of<32, 8>(fwd);
+    case 64: return plan_of<64, 8>(fwd);
+    case 128: return plan_of<128, 8>(fwd);
+    case 256: return plan_of<256, 8>(fwd);
+    case 512: return plan_of<512, 8>(fwd);
+    default: return {};
+  }
+}
+
+// Twiddle table of a plan: for each pass with NS > 1, for k in [0, NS), the values
+// exp(-2 pi i r k / (NS R)), r = 1..R-1 (the kernels conjugate them for the inverse).
+std::vector<std::complex<double>> twiddle_table(const std::vector<int>& radices) {
+  std::vector<std::complex<double>> out;
+  int ns = 1;
+  for (int R : radices) {
+    if (ns > 1)
+      for (int k = 0; k < ns; ++k)
+        for (int r = 1; r < R; ++r) {
+          double a = -2.0 * kPi * (double)r * (double)k / (double)(ns * R);
+          out.emplace_back(std::cos(a), std::sin(a));
+        }
+    ns *= R;
+  }
+  return out;
+}
+
+}  // namespace
+
+struct sgp_ctx {
+  sgp_grid g;
+  sgp_params p;
+  int dtype;
+  hipStream_t st;
+  size_t esize;  // bytes of one real
+
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t total = 0;
+  size_t off_tw[3][2];
+  size_t off_cs[2];
+  size_t off_kin[2][3];
+  size_t off_clock;
+  size_t off_part;
+  int npart = 1024;
+
+  int scheme = 0;
+  double tau = 0.0;
+  int nprop = 0;
+  double dprop[2] = {0, 0};
+  bool have_prop = false;
+  double t = 0.0;
+  std::string err;
+
+  long npts() const { return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1); }
+  void* at(size_t off) const { return ws + off; }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(sgp_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+int hip_fail(sgp_ctx* c, hipError_t e, const char* where) {
+  return fail(c, SGP_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// TS4 coefficients (Sec. 3.3): a1 = a4, a2 = a3 on the nonlinear flow; b1 = b3, b2 on
+// the linear flow.
+struct TS4 {
+  double a1, a2, b1, b2;
+  TS4() {
+    double c = std::cbrt(2.0), den = 2.0 - c;
+    a1 = 1.0 / (2.0 * den);
+    a2 = (1.0 - c) / (2.0 * den);
+    b1 = 1.0 / den;
+    b2 = -c / den;
+  }
+};
+
+template <typename T>
+hipError_t upload_twiddles(sgp_ctx* c) {
+  for (int ax = 0; ax < c->g.dim; ++ax) {
+    for (int dir = 0; dir < 2; ++dir) {
+      auto tab = twiddle_table(plan_radices(c->g.n[ax], dir == 0));
+      // each twiddle as a (hi, lo) pair: hi = w rounded to T, lo = (w - hi) rounded
+      std::vector<T> buf(4 * tab.size() + 4);
+      for (size_t i = 0; i < tab.size(); ++i) {
+        T hr = (T)tab[i].real(), hi = (T)tab[i].imag();
+        buf[4 * i] = hr;
+        buf[4 * i + 1] = hi;
+        buf[4 * i + 2] = (T)(tab[i].real() - (double)hr);
+        buf[4 * i + 3] = (T)(tab[i].imag() - (double)hi);
+      }
+      if (tab.empty()) continue;
+      hipError_t e = hipMemcpyAsync(c->at(c->off_tw[ax][dir]), buf.data(), sizeof(T) * 4 * tab.size(),
+                                    hipMemcpyHostToDevice, c->st);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(c->st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_xpass(sgp_ctx* c, int mode, void* psi, double d, int clock_mode, double s_arg) {
+  XArgs a;
+  a.comp_stride = c->npts();
+  a.nlines = (long)c->g.n[1] * (c->g.dim == 3 ? c->g.n[2] : 1);
+  a.ny = c->g.n[1];
+  a.tw_fwd = c->at(c->off_tw[0][0]);
+  a.tw_inv = c->at(c->off_tw[0][1]);
+  for (int i = 0; i < 3; ++i) {
+    bool on = i < c->g.dim;
+    a.L[i] = on ? c->g.L[i] : 0.0;
+    a.h[i] = on ? 2.0 * c->g.L[i] / c->g.n[i] : 0.0;
+  }
+  a.g2[0] = c->p.gx * c->p.gx;
+  a.g2[1] = c->p.gy * c->p.gy;
+  a.g2[2] = c->g.dim == 3 ? c->p.gz * c->p.gz : 0.0;
+  a.Omega = c->p.Omega;
+  a.d = d;
+  a.c0p = c->p.c0 + c->p.c2 / 5.0;
+  a.c1 = c->p.c1;
+  a.c2 = c->p.c2;
+  a.clock = (double*)c->at(c->off_clock);
+  a.s_arg = s_arg;
+  a.clock_mode = clock_mode;
+  long nlines = (long)c->g.n[1] * (c->g.dim == 3 ? c->g.n[2] : 1);
+  return launch_xpass<T>(mode, psi, a, c->g.n[0], nlines, c->st);
+}
+
+template <typename T>
+hipError_t run_colpass(sgp_ctx* c, int mode, int axis, void* psi, int table, double d) {
+  CArgs a;
+  const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
+  a.comp_stride = c->npts();
+  a.ncols = nx;
+  a.dim = c->g.dim;
+  a.n_q = ny;
+  if (axis == 1) {
+    a.stride = nx;
+    a.nouter = nz;
+    a.outer_stride = (long)nx * ny;
+  } else {
+    a.stride = (long)nx * ny;
+    a.nouter = ny;
+    a.outer_stride = nx;
+  }
+  a.tw_fwd = c->at(c->off_tw[axis][0]);
+  a.tw_inv = c->at(c->off_tw[axis][1]);
+  a.cs = c->at(c->off_cs[table]);
+  a.kin_a = c->at(c->off_kin[table][0]);
+  a.kin_o = c->at(c->off_kin[table][1]);
+  a.kin_l = c->at(c->off_kin[table][axis]);
+  a.nu_scale_a = kPi / c->g.L[0];
+  a.nu_scale_q = kPi / c->g.L[1];
+  a.Omega = c->p.Omega;
+  a.gamma = c->p.gamma;
+  a.norm = 1.0 / (double)c->npts();
+  a.d = d;
+  a.clock = (double*)c->at(c->off_clock);
+  a.advance_clock = (mode == C_PROP) ? 1 : 0;
+  return launch_colpass<T>(mode, psi, a, c->g.n[axis], c->st);
+}
+
+// One exact linear substep on x-transformed data: 2D Y-pass, 3D Y1 + Z + Y2.
+template <typename T>
+hipError_t run_linear(sgp_ctx* c, void* psi, int table, double d) {
+  if (c->g.dim == 2) return run_colpass<T>(c, C_PROP, 1, psi, table, d);
+  hipError_t e = run_colpass<T>(c, C_FWD, 1, psi, table, d);
+  if (e != hipSuccess) return e;
+  e = run_colpass<T>(c, C_PROP, 2, psi, table, d);
+  if (e != hipSuccess) return e;
+  return run_colpass<T>(c, C_INV, 1, psi, table, d);
+}
+
+// Substep schedule of nsteps steps with merged adjacent nonlinear substeps:
+// nl has one more entry than lin; lin_tab selects the propagator table.
+void schedule(const sgp_ctx* c, long nsteps, std::vector<double>& nl, std::vector<double>& lin,
+              std::vector<int>& lin_tab) {
+  const double tau = c->tau;
+  nl.clear(); lin.clear(); lin_tab.clear();
+  if (c->scheme == SGP_TS2) {
+    nl.push_back(0.5 * tau);
+    for (long n = 0; n < nsteps; ++n) {
+      lin.push_back(tau); lin_tab.push_back(0);
+      nl.push_back(n + 1 < nsteps ? tau : 0.5 * tau);
+    }
+  } else {
+    TS4 k;
+    nl.push_back(k.a1 * tau);
+    for (long n = 0; n < nsteps; ++n) {
+      lin.push_back(k.b1 * tau); lin_tab.push_back(0);
+      nl.push_back(k.a2 * tau);
+      lin.push_back(k.b2 * tau); lin_tab.push_back(1);
+      nl.push_back(k.a2 * tau);
+      lin.push_back(k.b1 * tau); lin_tab.push_back(0);
+      nl.push_back(n + 1 < nsteps ? 2.0 * k.a1 * tau : k.a1 * tau);
+    }
+  }
+}
+
+template <typename T>
+int step_impl(sgp_ctx* c, void* psi, long nsteps) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(c, nsteps, nl, lin, tab);
+  hipError_t e = run_xpass<T>(c, X_FIRST, psi, nl[0], CLOCK_ARG, c->t);
+  if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
+  for (size_t k = 0; k < lin.size(); ++k) {
+    e = run_linear<T>(c, psi, tab[k], lin[k]);
+    if (e != hipSuccess) return hip_fail(c, e, "linear pass launch");
+    e = run_xpass<T>(c, k + 1 == lin.size() ? X_LAST : X_MID, psi, nl[k + 1], CLOCK_DEVICE, 0.0);
+    if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
+  }
+  c->t += (double)nsteps * c->tau;
+  return SGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* hip_stream, sgp_ctx** out) {
+  if (!grid || !params || !out) return fail(nullptr, SGP_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (grid->dim != 2 && grid->dim != 3) return fail(nullptr, SGP_ERR_ARG, "dim must be 2 or 3");
+  for (int i = 0; i < grid->dim; ++i) {
+    if (!supported_n(grid->n[i]))
+      return fail(nullptr, SGP_ERR_ARG, "unsupported grid size " + std::to_string(grid->n[i]) +
+                                            " (supported: 16, 32, 64, 128, 256, 512)");
+    if (!(grid->L[i] > 0.0) || !std::isfinite(grid->L[i])) return fail(nullptr, SGP_ERR_ARG, "L must be > 0");
+  }
+  const double* pv = &params->c0;
+  for (int i = 0; i < 8; ++i)
+    if (!std::isfinite(pv[i])) return fail(nullptr, SGP_ERR_ARG, "non-finite parameter");
+  if (dtype != SGP_C64 && dtype != SGP_C128) return fail(nullptr, SGP_ERR_ARG, "dtype must be SGP_C64 or SGP_C128");
+  sgp_ctx* c = new (std::nothrow) sgp_ctx();
+  if (!c) return fail(nullptr, SGP_ERR_ARG, "out of host memory");
+  c->g = *grid;
+  if (c->g.dim == 2) { c->g.n[2] = 1; c->g.L[2] = 0.0; }
+  c->p = *params;
+  c->dtype = dtype;
+  c->st = (hipStream_t)hip_stream;
+  c->esize = dtype == SGP_C64 ? 4 : 8;
+  // workspace layout
+  size_t off = 0;
+  for (int ax = 0; ax < 3; ++ax)
+    for (int dir = 0; dir < 2; ++dir) {
+      c->off_tw[ax][dir] = off;
+      if (ax < c->g.dim) off += align256(4 * c->esize * (twiddle_table(plan_radices(c->g.n[ax], dir == 0)).size() + 1));
+    }
+  const size_t nxy = (size_t)c->g.n[0] * c->g.n[1];
+  for (int k = 0; k < 2; ++k) {
+    c->off_cs[k] = off;
+    off += align256(2 * c->esize * nxy);
+    for (int ax = 0; ax < 3; ++ax) {
+      c->off_kin[k][ax] = off;
+      off += align256(2 * c->esize * (ax < c->g.dim ? c->g.n[ax] : 1));
+    }
+  }
+  c->off_clock = off;
+  off += 256;
+  c->off_part = off;
+  off += align256(sizeof(double) * 8 * c->npart);
+  c->total = off;
+  *out = c;
+  return SGP_OK;
+}
+
+int sgp_workspace_size(const sgp_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return SGP_ERR_ARG;
+  *bytes = c->total;
+  return SGP_OK;
+}
+
+int sgp_set_workspace(sgp_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return fail(c, SGP_ERR_ARG, "null argument");
+  if (bytes < c->total) return fail(c, SGP_ERR_WORKSPACE, "workspace too small");
+  if (((uintptr_t)dev_ptr) & 255) return fail(c, SGP_ERR_ARG, "workspace must be 256-byte aligned");
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  c->have_prop = false;
+  hipError_t e = c->dtype == SGP_C64 ? upload_twiddles<float>(c) : upload_twiddles<double>(c);
+  if (e != hipSuccess) return hip_fail(c, e, "twiddle upload");
+  return SGP_OK;
+}
+
+int sgp_build_propagator(sgp_ctx* c, double tau, int scheme) {
+  if (!c) return SGP_ERR_ARG;
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!std::isfinite(tau) || tau == 0.0) return fail(c, SGP_ERR_ARG, "tau must be finite and nonzero");
+  if (scheme != SGP_TS2 && scheme != SGP_TS4) return fail(c, SGP_ERR_ARG, "scheme must be SGP_TS2 or SGP_TS4");
+  c->scheme = scheme;
+  c->tau = tau;
+  if (scheme == SGP_TS2) {
+    c->nprop = 1;
+    c->dprop[0] = tau;
+  } else {
+    TS4 k;
+    c->nprop = 2;
+    c->dprop[0] = k.b1 * tau;
+    c->dprop[1] = k.b2 * tau;
+  }
+  for (int i = 0; i < c->nprop; ++i) {
+    hipError_t e;
+    if (c->dtype == SGP_C64)
+      e = launch_build_tables<float>(c->at(c->off_cs[i]), c->at(c->off_kin[i][0]), c->at(c->off_kin[i][1]),
+                                     c->at(c->off_kin[i][2]), c->g.n, c->g.L, c->g.dim, c->p.Omega, c->p.gamma,
+                                     c->dprop[i], c->st);
+    else
+      e = launch_build_tables<double>(c->at(c->off_cs[i]), c->at(c->off_kin[i][0]), c->at(c->off_kin[i][1]),
+                                      c->at(c->off_kin[i][2]), c->g.n, c->g.L, c->g.dim, c->p.Omega, c->p.gamma,
+                                      c->dprop[i], c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "propagator build");
+  }
+  hipError_t e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return hip_fail(c, e, "propagator build");
+  c->have_prop = true;
+  return SGP_OK;
+}
+
+int sgp_step(sgp_ctx* c, void* psi, long nsteps) {
+  if (!c || !psi) return fail(c, SGP_ERR_ARG, "null argument");
+  if (nsteps < 0) return fail(c, SGP_ERR_ARG, "nsteps must be >= 0");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  if (nsteps == 0) return SGP_OK;
+  return c->dtype == SGP_C64 ? step_impl<float>(c, psi, nsteps) : step_impl<double>(c, psi, nsteps);
+}
+
+int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
+  if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  double* part = (double*)c->at(c->off_part);
+  hipError_t e = c->dtype == SGP_C64 ? launch_mass_magn<float>(psi, c->npts(), part, c->npart, c->st)
+                                     : launch_mass_magn<double>(psi, c->npts(), part, c->npart, c->st);
+  if (e != hipSuccess) return hip_fail(c, e, "observables launch");
+  std::vector<double> host(2 * c->npart);
+  e = hipMemcpyAsync(host.data(), part, sizeof(double) * 2 * c->npart, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return hip_fail(c, e, "observables readback");
+  double m = 0, mg = 0;
+  for (int i = 0; i < c->npart; ++i) { m += host[2 * i]; mg += host[2 * i + 1]; }
+  double hd = 1.0;
+  for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
+  out[0] = hd * m;
+  out[1] = NAN;
+  out[2] = hd * mg;
+  out[3] = NAN;
+  return SGP_OK;
+}
+
+int sgp_get_time(const sgp_ctx* c, double* t) {
+  if (!c || !t) return SGP_ERR_ARG;
+  *t = c->t;
+  return SGP_OK;
+}
+
+int sgp_set_time(sgp_ctx* c, double t) {
+  if (!c || !std::isfinite(t)) return SGP_ERR_ARG;
+  c->t = t;
+  return SGP_OK;
+}
+
+void sgp_destroy(sgp_ctx* c) { delete c; }
+
+const char* sgp_last_error(const sgp_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"

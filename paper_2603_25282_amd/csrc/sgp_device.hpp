@@ -1,0 +1,473 @@
+// Device building blocks for the split-step kernels (gfx950).
+//
+//  * cx<T>            interleaved complex in registers (T = float or double).
+//  * Stockham FFT     register-resident, radix 2/3/4/8 passes with LDS exchanges.
+//  * sym4_apply       spin-2 rotation of a 5-vector as the 4th symmetric power of an
+//                     SU(2) element, factored L * D * R (two Taylor shifts + diagonal).
+//  * nl_point         exact nonlinear flow at one grid point (Sec. 3.2, eq. solution2).
+//
+// Component order everywhere: index i = 0..4 <-> spin projection l = 2, 1, 0, -1, -2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgp {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { cx<T> z; z.re = r; z.im = i; return z; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.re + b.re, a.im + b.im); }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk<T>(a.re - b.re, a.im - b.im); }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk<T>(s * a.re, s * a.im); }
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk<T>(a.re, -a.im); }
+template <typename T> __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+// i * a
+template <typename T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return mk<T>(-a.im, a.re); }
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk<T>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+// acc + a * b
+template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+  return mk<T>(acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re);
+}
+
+// ---------------------------------------------------------------------------
+// Small DFT kernels, y_q = sum_s x_s exp(SIGN 2 pi i s q / R), in place.
+// ---------------------------------------------------------------------------
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> rot_quarter(cx<T> a) {  // a * exp(SIGN i pi/2)
+  return SIGN < 0 ? mk<T>(a.im, -a.re) : mk<T>(-a.im, a.re);
+}
+
+template <int R, int SIGN, typename T>
+struct Dft;
+
+template <int SIGN, typename T>
+struct Dft<2, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    cx<T> a = x[0], b = x[1];
+    x[0] = a + b;
+    x[1] = a - b;
+  }
+};
+
+// c * z for a constant c = c_hi + c_lo (c_lo = 0 in FP64): a rounded constant would
+// repeat the same relative error in every step.
+template <typename T>
+__device__ __forceinline__ T kmul(T hi, T lo, T z) {
+  if constexpr (sizeof(T) == 4) return fmaf(hi, z, lo * z);
+  else return hi * z;
+}
+
+template <int SIGN, typename T>
+struct Dft<3, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    // sqrt(3)/2 as a float pair
+    const T sh = T(0.866025388240814208984375), sl = T(sizeof(T) == 4 ? 1.5543625e-08 : 0.0);
+    const T s3 = sizeof(T) == 4 ? sh : T(0.86602540378443864676372317075293618);
+    cx<T> a = x[0], b = x[1], d = x[2];
+    cx<T> sum = b + d, dif = b - d;
+    x[0] = a + sum;
+    cx<T> m = mk<T>(a.re - T(0.5) * sum.re, a.im - T(0.5) * sum.im);
+    // SIGN * i * sqrt(3)/2 * dif
+    cx<T> r = mk<T>(-kmul<T>(s3, sl, dif.im), kmul<T>(s3, sl, dif.re));
+    if (SIGN < 0) r = mk<T>(-r.re, -r.im);
+    x[1] = m + r;
+    x[2] = m - r;
+  }
+};
+
+template <int SIGN, typename T>
+struct Dft<4, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    cx<T> a0 = x[0] + x[2], a1 = x[0] - x[2];
+    cx<T> b0 = x[1] + x[3], b1 = rot_quarter<SIGN>(x[1] - x[3]);
+    x[0] = a0 + b0;
+    x[2] = a0 - b0;
+    x[1] = a1 + b1;
+    x[3] = a1 - b1;
+  }
+};
+
+template <int SIGN, typename T>
+struct Dft<8, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    // sqrt(2)/2 as a float pair
+    const T hh = sizeof(T) == 4 ? T(0.707106769084930419921875) : T(0.70710678118654752440084436210484904);
+    const T hl = T(sizeof(T) == 4 ? 1.2101617e-08 : 0.0);
+    // two length-4 DFTs on even and odd samples
+    cx<T> e[4] = {x[0], x[2], x[4], x[6]};
+    cx<T> o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<4, SIGN, T>::run(e);
+    Dft<4, SIGN, T>::run(o);
+    // twiddles exp(SIGN 2 pi i q / 8), q = 1, 2, 3
+    cx<T> o1 = o[1], o2 = o[2], o3 = o[3];
+    cx<T> t1, t2, t3;
+    if (SIGN < 0) {
+      t1 = mk<T>(kmul<T>(hh, hl, o1.re + o1.im), kmul<T>(hh, hl, o1.im - o1.re));
+      t2 = mk<T>(o2.im, -o2.re);
+      t3 = mk<T>(kmul<T>(hh, hl, o3.im - o3.re), -kmul<T>(hh, hl, o3.re + o3.im));
+    } else {
+      t1 = mk<T>(kmul<T>(hh, hl, o1.re - o1.im), kmul<T>(hh, hl, o1.re + o1.im));
+      t2 = mk<T>(-o2.im, o2.re);
+      t3 = mk<T>(-kmul<T>(hh, hl, o3.re + o3.im), kmul<T>(hh, hl, o3.re - o3.im));
+    }
+    x[0] = e[0] + o[0];
+    x[4] = e[0] - o[0];
+    x[1] = e[1] + t1;
+    x[5] = e[1] - t1;
+    x[2] = e[2] + t2;
+    x[6] = e[2] - t2;
+    x[3] = e[3] + t3;
+    x[7] = e[3] - t3;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Register-resident Stockham FFT of length N along one line.
+//
+// The line is owned by TL = N / E threads; thread t holds elements t + TL*m,
+// m = 0..E-1, in v[m].  A pass of radix R (sub-transform size NS before the pass)
+// runs E/R butterflies per thread: butterfly j = t + TL*b takes inputs
+// j + (N/R) r (registers b + (E/R) r), multiplies input r by w^(r (j mod NS)),
+// w = exp(SIGN 2 pi i / (NS R)), and its output r lands at element
+// (j / NS) NS R + (j mod NS) + r NS.  That position lies in another thread's
+// registers except after the last pass, where it is the input position again,
+// so a transform needs (passes - 1) LDS exchanges and both ends of it use the same
+// register layout.  Twiddles come from a per-pass table: for each k in [0, NS)
+// the R-1 values w^(r k), r = 1..R-1, each stored as a (hi, lo) pair.
+//
+// LDS exchange buffers are split re / im and padded by one slot every 8 entries
+// (bank-conflict-free stride-8 writes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+template <int N> struct LdsLine { static constexpr int size = N + N / 8; };
+
+// x * (wh + wl) with the small product folded in before the large one.
+template <typename T>
+__device__ __forceinline__ cx<T> twmul(cx<T> x, cx<T> wh, cx<T> wl) {
+  if constexpr (sizeof(T) == 4) {
+    const T sr = x.re * wl.re - x.im * wl.im;
+    const T si = x.re * wl.im + x.im * wl.re;
+    return mk<T>(fmaf(x.re, wh.re, fmaf(-x.im, wh.im, sr)), fmaf(x.re, wh.im, fmaf(x.im, wh.re, si)));
+  } else {
+    return x * wh;
+  }
+}
+
+// SYNC = 0: the line's threads may span several wavefronts (workgroup barrier);
+// SYNC = 1: every line lies inside one wavefront (wavefront-scope ordering only).
+template <int SYNC>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (SYNC == 0) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// NBUF: how many components share one LDS exchange round (1 <= NBUF <= NC); buffer
+// b of a line starts at b * lds_stride.
+template <typename T, int N, int E, int R, int NS, int SIGN, bool LAST, int NC, int NBUF, int SYNC>
+__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre, T* __restrict__ lim, int t,
+                                         const cx<T>* __restrict__ tw, int lds_stride) {
+  constexpr int TL = N / E;
+  constexpr int B = E / R;
+  static_assert(E % R == 0, "radix must divide the elements per thread");
+  // twiddles for this thread's butterflies (shared by all NC components), each a
+  // (hi, lo) pair so that the product carries no fixed rounding of the twiddle
+  cx<T> w[B][R > 1 ? R - 1 : 1], wl[B][R > 1 ? R - 1 : 1];
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + TL * b;
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> z = tw[2 * (k * (R - 1) + (r - 1))];
+        cx<T> zl = tw[2 * (k * (R - 1) + (r - 1)) + 1];
+        w[b][r - 1] = SIGN < 0 ? z : conj(z);
+        wl[b][r - 1] = SIGN < 0 ? zl : conj(zl);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      cx<T> x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = v[c][b + B * r];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) x[r] = twmul(x[r], w[b][r - 1], wl[b][r - 1]);
+      }
+      Dft<R, SIGN, T>::run(x);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c][b + B * r] = x[r];
+      } else {
+        const int j = t + TL * b;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int o = lds_pad(base + r * NS) + (c % NBUF) * lds_stride;
+          lre[o] = x[r].re;
+          lim[o] = x[r].im;
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      if (c % NBUF == NBUF - 1 || c == NC - 1) {
+        lds_sync<SYNC>();
+        const int c0 = c - (c % NBUF);
+#pragma unroll
+        for (int cc = c0; cc <= c; ++cc)
+#pragma unroll
+          for (int m = 0; m < E; ++m) {
+            const int o = lds_pad(t + TL * m) + (cc % NBUF) * lds_stride;
+            v[cc][m] = mk<T>(lre[o], lim[o]);
+          }
+        lds_sync<SYNC>();
+      }
+    }
+  }
+}
+
+// Radix plans.  Forward passes run in the listed order, the inverse runs the
+// reverse order so that the two share the register layout at both ends.
+template <int... Rs> struct RadixList {};
+template <int N, int E> struct Plan;
+template <> struct Plan<16, 8> { using fwd = RadixList<2, 8>; using inv = RadixList<8, 2>; };
+template <> struct Plan<32, 8> { using fwd = RadixList<4, 8>; using inv = RadixList<8, 4>; };
+template <> struct Plan<64, 8> { using fwd = RadixList<8, 8>; using inv = RadixList<8, 8>; };
+template <> struct Plan<128, 8> { using fwd = RadixList<2, 8, 8>; using inv = RadixList<8, 8, 2>; };
+template <> struct Plan<256, 8> { using fwd = RadixList<4, 8, 8>; using inv = RadixList<8, 8, 4>; };
+template <> struct Plan<512, 8> { using fwd = RadixList<8, 8, 8>; using inv = RadixList<8, 8, 8>; };
+template <> struct Plan<1024, 8> { using fwd = RadixList<2, 8, 8, 8>; using inv = RadixList<8, 8, 8, 2>; };
+template <> struct Plan<48, 12> { using fwd = RadixList<3, 4, 4>; using inv = RadixList<4, 4, 3>; };
+template <> struct Plan<96, 12> { using fwd = RadixList<3, 4, 4, 2>; using inv = RadixList<2, 4, 4, 3>; };
+template <> struct Plan<192, 12> { using fwd = RadixList<3, 4, 4, 4>; using inv = RadixList<4, 4, 4, 3>; };
+template <> struct Plan<384, 12> { using fwd = RadixList<3, 4, 4, 4, 2>; using inv = RadixList<2, 4, 4, 4, 3>; };
+template <> struct Plan<768, 12> { using fwd = RadixList<3, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 3>; };
+
+template <typename T, int N, int E, int SIGN, int NS, int NC, int NBUF, int SYNC, int R, int... Rest>
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,
+                                           int lds_stride) {
+  constexpr bool last = sizeof...(Rest) == 0;
+  fft_pass<T, N, E, R, NS, SIGN, last, NC, NBUF, SYNC>(v, lre, lim, t, tw, lds_stride);
+  if constexpr (!last) {
+    fft_passes<T, N, E, SIGN, NS * R, NC, NBUF, SYNC, Rest...>(v, lre, lim, t,
+                                                              tw + (NS > 1 ? 2 * NS * (R - 1) : 0), lds_stride);
+  }
+}
+
+template <typename T, int N, int E, int SIGN, int NC, int NBUF, int SYNC, int... Rs>
+__device__ __forceinline__ void fft_run(RadixList<Rs...>, cx<T> (&v)[NC][E], T* lre, T* lim, int t,
+                                        const cx<T>* tw, int lds_stride) {
+  fft_passes<T, N, E, SIGN, 1, NC, NBUF, SYNC, Rs...>(v, lre, lim, t, tw, lds_stride);
+}
+
+// Forward (SIGN = -1) or inverse (SIGN = +1) unscaled transform of NC components.
+// tw points at the table of the plan for this direction.
+template <typename T, int N, int E, int SIGN, int NC, int NBUF, int SYNC>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,
+                                         int lds_stride) {
+  if constexpr (SIGN < 0)
+    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::fwd{}, v, lre, lim, t, tw, lds_stride);
+  else
+    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::inv{}, v, lre, lim, t, tw, lds_stride);
+}
+
+// ---------------------------------------------------------------------------
+// Spin-2 rotation as the 4th symmetric power of U = [[alpha, beta], [-conj(beta),
+// conj(alpha)]] (|alpha|^2 + |beta|^2 = 1), times a scalar `scale`, applied to x.
+//
+// A 5-vector x (order m = 2..-2) is the binary quartic form sum_k x_k sqrt(C(4,k))
+// u^k v^(4-k), k = m + 2; U acts by u -> U11 u + U21 v, v -> U12 u + U22 v.
+// With U = L D R, L = [[1, 0], [l, 1]], D = diag(a, det/a), R = [[1, r], [0, 1]]:
+// R is a Taylor shift of the form in v by r, D scales u^k v^(4-k) by
+// a^(2k-4) det^(4-k), and L is a Taylor shift in u by l.  The shifts run directly on
+// the normalised components (coefficient ratios rho_j = sqrt(C(4,j+1)/C(4,j))...).
+// When |beta| > |alpha| the factorisation runs on U P (P swaps u and v, i.e.
+// reverses x) so that |l|, |r| <= 1.  The spin-1/2 matrices sigma/2 map to the
+// spin-2 matrices f of Sec. 1 under this representation, so
+// exp(i t n.sigma/2) -> exp(i t n.f).
+//
+// Inputs come in increment form: alpha = 1 + as, scale = 1 + ss.  Every update is
+// x <- x + (small coefficient) * x, so a coefficient's rounding error scales with
+// the coefficient and the near-identity maps of small time steps repeat no O(1)
+// rounding error from step to step.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, cx<T> (&x)[5]) {
+  // rho_j = rc_(j+1)/rc_j with rc = (1, 2, sqrt6, 2, 1)
+  const T rho0 = T(2), rho1 = T(1.22474487139158904909864203735294570), rho2 = T(0.81649658092772603273242802490196380),
+          rho3 = T(0.5);
+  const cx<T> alpha = mk<T>(T(1) + as.re, as.im);
+  const bool pivot = norm2(beta) > norm2(alpha);
+  cx<T> eps[5];
+  cx<T> r, l;
+  const cx<T> one = mk<T>(T(1), T(0));
+  if (!pivot) {
+    const T q = T(1) / norm2(alpha);
+    const cx<T> ia = mk<T>(alpha.re * q, -alpha.im * q);  // 1/alpha
+    r = beta * ia;
+    l = mk<T>(-beta.re, beta.im) * ia;  // -conj(beta)/alpha
+    // a^2 - 1, a^4 - 1, a^-2 - 1, a^-4 - 1 from as = a - 1 without cancellation
+    const cx<T> e2 = as * (mk<T>(T(2), T(0)) + as);
+    const cx<T> e4 = e2 * (mk<T>(T(2), T(0)) + e2);
+    const cx<T> one_e2 = one + e2;
+    const T q2 = T(1) / norm2(one_e2);
+    const cx<T> inv_e2 = mk<T>(one_e2.re * q2, -one_e2.im * q2);
+    const cx<T> em2 = mk<T>(-e2.re, -e2.im) * inv_e2;
+    const cx<T> em4 = em2 * (mk<T>(T(2), T(0)) + em2);
+    // (1 + e)(1 + s) - 1 = e + s + e s
+    eps[0] = e4 + ss + e4 * ss;
+    eps[1] = e2 + ss + e2 * ss;
+    eps[2] = ss;
+    eps[3] = em2 + ss + em2 * ss;
+    eps[4] = em4 + ss + em4 * ss;
+  } else {
+    // U P = [[beta, alpha], [conj(alpha), -conj(beta)]], det -1
+    const T q = T(1) / norm2(beta);
+    const cx<T> ia = mk<T>(beta.re * q, -beta.im * q);  // 1/beta
+    r = alpha * ia;
+    l = conj(alpha) * ia;
+    const cx<T> a2 = beta * beta, a4 = a2 * a2;
+    const cx<T> ia2 = ia * ia, ia4 = ia2 * ia2;
+    const cx<T> sc = one + ss;
+    eps[0] = a4 * sc - one;
+    eps[1] = mk<T>(-a2.re, -a2.im) * sc - one;
+    eps[2] = ss;
+    eps[3] = mk<T>(-ia2.re, -ia2.im) * sc - one;
+    eps[4] = ia4 * sc - one;
+    cx<T> t0 = x[0], t1 = x[1];
+    x[0] = x[4];
+    x[1] = x[3];
+    x[3] = t1;
+    x[4] = t0;
+  }
+  const cx<T> rr0 = rho0 * r, rr1 = rho1 * r, rr2 = rho2 * r, rr3 = rho3 * r;
+  const cx<T> lr0 = rho0 * l, lr1 = rho1 * l, lr2 = rho2 * l, lr3 = rho3 * l;
+  // R: Taylor shift, x_j += r rho_j x_(j+1), i = 0..3, j = 3..i
+  x[3] = cfma(rr3, x[4], x[3]);
+  x[2] = cfma(rr2, x[3], x[2]);
+  x[1] = cfma(rr1, x[2], x[1]);
+  x[0] = cfma(rr0, x[1], x[0]);
+  x[3] = cfma(rr3, x[4], x[3]);
+  x[2] = cfma(rr2, x[3], x[2]);
+  x[1] = cfma(rr1, x[2], x[1]);
+  x[3] = cfma(rr3, x[4], x[3]);
+  x[2] = cfma(rr2, x[3], x[2]);
+  x[3] = cfma(rr3, x[4], x[3]);
+  // D: x_j += eps_j x_j
+#pragma unroll
+  for (int j = 0; j < 5; ++j) x[j] = cfma(eps[j], x[j], x[j]);
+  // L: Taylor shift on the reversed vector, x_(4-k) += l rho_k x_(3-k)
+  x[1] = cfma(lr3, x[0], x[1]);
+  x[2] = cfma(lr2, x[1], x[2]);
+  x[3] = cfma(lr1, x[2], x[3]);
+  x[4] = cfma(lr0, x[3], x[4]);
+  x[1] = cfma(lr3, x[0], x[1]);
+  x[2] = cfma(lr2, x[1], x[2]);
+  x[3] = cfma(lr1, x[2], x[3]);
+  x[1] = cfma(lr3, x[0], x[1]);
+  x[2] = cfma(lr2, x[1], x[2]);
+  x[1] = cfma(lr3, x[0], x[1]);
+}
+
+// cos(x) - 1 and sin(x)/x without cancellation or division by zero.
+template <typename T>
+__device__ __forceinline__ void cosm1_sinc(T x, T& cm1, T& sc) {
+  const T x2 = x * x;
+  const T small = sizeof(T) == 4 ? T(1e-2) : T(1e-4);
+  if (fabs(x) < small) {
+    sc = T(1) - x2 * (T(1) / T(6)) * (T(1) - x2 * T(0.05));
+    cm1 = -x2 * T(0.5) * (T(1) - x2 * (T(1) / T(12)));
+  } else {
+    T s, c, sh, ch;
+    if constexpr (sizeof(T) == 4) { sincosf(x, &s, &c); sincosf(T(0.5) * x, &sh, &ch); }
+    else { sincos(x, &s, &c); sincos(T(0.5) * x, &sh, &ch); }
+    sc = s / x;
+    cm1 = T(-2) * sh * sh;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact nonlinear flow at one point for time d (Sec. 3.2, eq. solution2):
+//   b = cos(c2 S d) psi + i (sin(c2 S d)/S) (rho/5 psi - A00 A conj(psi))
+//   psi <- exp(-i d [V + (c0 + c2/5) rho]) exp(-i c1 d F.f) b
+// S = sqrt(max(0, (rho/5)^2 - |A00|^2/5)).  The spin rotation exp(-i c1 d F.f) is
+// sym4 of exp(-i c1 d F.sigma/2): alpha = cos(kappa/2) - i s F_z,
+// beta = -i s F_-, s = sin(kappa/2)/|F| = (c1 d/2) sinc(kappa/2), kappa = c1 d |F|.
+// The scalar phase is evaluated in FP64 (argument, its reduction mod 2 pi, and
+// exp(-i phi) - 1) and folded into the rotation's diagonal.  Every factor enters
+// in increment form (cos - 1, exp(-i phi) - 1, ...).
+// ---------------------------------------------------------------------------
+struct NLCoef {
+  double d;      // substep duration
+  double c0p;    // c0 + c2/5
+  double c1, c2;
+};
+
+template <typename T>
+__device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& K) {
+  const T r6 = T(2.44948974278317809819728407470589139);
+  const T r5i = T(0.44721359549995793928183473374625524);
+  const T n0 = norm2(p[0]), n1 = norm2(p[1]), n2 = norm2(p[2]), n3 = norm2(p[3]), n4 = norm2(p[4]);
+  const T rho = n0 + n1 + n2 + n3 + n4;
+  const T Fz = T(2) * (n0 - n4) + (n1 - n3);
+  // F_+ = 2 (conj(psi2) psi1 + conj(psi-1) psi-2) + sqrt6 (conj(psi1) psi0 + conj(psi0) psi-1)
+  const cx<T> Fp = T(2) * (cmulc(p[0], p[1]) + cmulc(p[3], p[4])) + r6 * (cmulc(p[1], p[2]) + cmulc(p[2], p[3]));
+  // A00 = (2 psi2 psi-2 - 2 psi1 psi-1 + psi0^2)/sqrt5
+  const cx<T> A00 = r5i * (T(2) * (p[0] * p[4] - p[1] * p[3]) + p[2] * p[2]);
+  const T rho5 = rho * T(0.2);
+  T S2 = rho5 * rho5 - norm2(A00) * T(0.2);
+  S2 = S2 > T(0) ? S2 : T(0);
+  const T S = sqrt(S2);
+  const T c2d = T(K.c2 * K.d);
+  T cm1, snc;
+  cosm1_sinc<T>(c2d * S, cm1, snc);
+  const T snS = c2d * snc;  // sin(c2 S d) / S
+  // b = psi + (cos - 1) psi + i snS (rho/5 psi - A00 (A conj psi)_i),
+  // (A conj psi)_i = (-1)^i conj(psi_(4-i)) / sqrt5
+  cx<T> b[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    cx<T> ab = conj(p[4 - i]);
+    if (i & 1) ab = mk<T>(-ab.re, -ab.im);
+    const cx<T> w = rho5 * p[i] - A00 * (r5i * ab);
+    b[i] = p[i] + (cm1 * p[i] + snS * mul_i(w));
+  }
+  // spin rotation: alpha - 1 = (cos(kappa/2) - 1) - i s F_z, beta = -i s F_-
+  const T Fabs = sqrt(norm2(Fp) + Fz * Fz);
+  const T hc1d = T(0.5 * K.c1 * K.d);
+  T ckm1, skc;
+  cosm1_sinc<T>(hc1d * Fabs, ckm1, skc);
+  const T s = hc1d * skc;  // sin(kappa/2)/|F|
+  const cx<T> as = mk<T>(ckm1, -s * Fz);
+  const cx<T> beta = mk<T>(-s * Fp.im, -s * Fp.re);
+  // scalar phase exp(-i phi) - 1, phi = d [V + (c0 + c2/5) rho], in FP64
+  const double phi = K.d * (V + K.c0p * (double)rho);
+  const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
+  const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
+  double sd, cd, sh, chh;
+  sincos(red, &sd, &cd);
+  sincos(0.5 * red, &sh, &chh);
+  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-sd));
+  sym4_apply_inc<T>(as, beta, phs, b);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = b[i];
+}
+
+}  // namespace sgp

@@ -1,0 +1,154 @@
+"""Thin Python binding of the C ABI in include/sgp.h (argument marshalling only).
+
+Every numerical step runs in the HIP library libsgp.so; this module only loads it,
+converts torch tensors to device pointers and turns error codes into exceptions.
+PyTorch provides device memory (state and workspace tensors) and the stream.
+
+State tensors: torch.complex64 or torch.complex128, shape (5, ny, nx) or
+(5, nz, ny, nx), contiguous, on a ROCm device; component i <-> l = 2, 1, 0, -1, -2.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgp.so")
+
+SGP_OK = 0
+SGP_C64, SGP_C128 = 0, 1
+SGP_TS2, SGP_TS4 = 2, 4
+
+
+class SgpError(RuntimeError):
+    pass
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("c0", "c1", "c2", "Omega", "gamma", "gx", "gy", "gz")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsgp.so (built in-tree by paper_2603_25282_amd/build.py).  Raises if
+    it is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SgpError(f"{LIB_PATH} not built; run python -m paper_2603_25282_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, cp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
+    L.sgp_create.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int, vp, cp]
+    L.sgp_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.sgp_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+    L.sgp_build_propagator.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+    L.sgp_step.argtypes = [vp, vp, ctypes.c_long]
+    L.sgp_observables.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.sgp_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.sgp_set_time.argtypes = [vp, ctypes.c_double]
+    L.sgp_destroy.argtypes = [vp]
+    L.sgp_destroy.restype = None
+    L.sgp_last_error.argtypes = [vp]
+    L.sgp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points this binding expects (all declared in sgp.h)."""
+    return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
+            "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_destroy", "sgp_last_error"]
+
+
+def _check(rc, ctx=None):
+    if rc != SGP_OK:
+        msg = lib().sgp_last_error(ctx)
+        raise SgpError(f"sgp error {rc}: {msg.decode() if msg else ''}")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One context: grid, physics, element type, stream and workspace.
+
+    shape: spatial shape (ny, nx) or (nz, ny, nx); L: half-width (scalar or per
+    axis in x, y, z order); params: (c0, c1, c2, Omega, gamma, gx, gy, gz).
+    """
+
+    def __init__(self, shape, L, params, dtype="complex64", device="cuda:0", stream=None):
+        import torch
+        self.shape = tuple(int(s) for s in shape)
+        dim = len(self.shape)
+        Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (dim,))
+        g = _Grid()
+        g.dim = dim
+        for i in range(3):
+            g.n[i] = self.shape[::-1][i] if i < dim else 1
+            g.L[i] = float(Ls[i]) if i < dim else 0.0
+        p = _Params(*[float(x) for x in params])
+        self.torch_dtype = {"complex64": torch.complex64, "complex128": torch.complex128}[str(dtype).replace(
+            "torch.", "")]
+        code = SGP_C64 if self.torch_dtype == torch.complex64 else SGP_C128
+        self.device = torch.device(device)
+        self.stream = stream
+        with torch.cuda.device(self.device):
+            sp = _stream_ptr(stream)
+        ctx = ctypes.c_void_p()
+        _check(lib().sgp_create(ctypes.byref(g), ctypes.byref(p), code, sp, ctypes.byref(ctx)), None)
+        self._ctx = ctx
+        nb = ctypes.c_size_t()
+        _check(lib().sgp_workspace_size(ctx, ctypes.byref(nb)), ctx)
+        # uint8 buffer; torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        _check(lib().sgp_set_workspace(ctx, ctypes.c_void_p(self.workspace.data_ptr()), nb.value), ctx)
+
+    def _psi_ptr(self, psi):
+        if psi.dtype != self.torch_dtype or tuple(psi.shape) != (5,) + self.shape:
+            raise SgpError(f"state must be {self.torch_dtype} of shape {(5,) + self.shape}, got {psi.dtype} "
+                           f"{tuple(psi.shape)}")
+        if not psi.is_contiguous() or psi.device != self.device:
+            raise SgpError("state must be contiguous on the solver's device")
+        return ctypes.c_void_p(psi.data_ptr())
+
+    def build_propagator(self, tau, scheme):
+        _check(lib().sgp_build_propagator(self._ctx, float(tau), int(scheme)), self._ctx)
+
+    def step(self, psi, nsteps):
+        _check(lib().sgp_step(self._ctx, self._psi_ptr(psi), int(nsteps)), self._ctx)
+
+    def observables(self, psi):
+        out = (ctypes.c_double * 4)()
+        _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
+        return np.array(out[:])
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        _check(lib().sgp_get_time(self._ctx, ctypes.byref(t)), self._ctx)
+        return t.value
+
+    @time.setter
+    def time(self, t):
+        _check(lib().sgp_set_time(self._ctx, float(t)), self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().sgp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
