@@ -19,9 +19,10 @@
  * N points per axis, h = 2L/N, x_j = -L + j h; wavenumbers nu_p = pi p / L,
  * p in [-N/2, N/2 - 1] (the Nyquist mode keeps nu = -pi N/(2L)).
  *
- * State layout (device memory, owned by the caller): [5][nz][ny][nx] complex,
- * interleaved (re, im), x fastest; component i = 0..4 holds spin projection
- * l = 2, 1, 0, -1, -2.  Element type: complex64 (SGP_C64) or complex128 (SGP_C128).
+ * State layout (device memory, owned by the caller): [nz][ny][nx][5] complex,
+ * interleaved (re, im), the 5 components of a grid point adjacent, then x, y, z;
+ * component i = 0..4 holds spin projection l = 2, 1, 0, -1, -2.  Element type:
+ * complex64 (SGP_C64) or complex128 (SGP_C128).
  *
  * Memory: the library allocates no device memory.  The caller asks for
  * sgp_workspace_size() bytes, allocates them (e.g. a torch tensor), and hands them
@@ -61,7 +62,7 @@ enum { SGP_TS2 = 2, SGP_TS4 = 4 };   /* time composition (Sec. 3.3) */
 typedef struct sgp_ctx sgp_ctx;
 
 /* Grid: dim = 2 or 3; n[0..dim-1] = points along x, y[, z]; L[] = half-widths.
- * Supported n per axis: 16, 32, 64, 128, 256, 512 (and 384 along x/y in 2D). */
+ * Supported n per axis: 16, 32, 64, 128, 256, 512. */
 typedef struct {
   int dim;
   int n[3];
@@ -113,6 +114,20 @@ int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
 /* Rotation clock t (the time of the rotating frame the state lives in). */
 int sgp_get_time(const sgp_ctx* ctx, double* t);
 int sgp_set_time(sgp_ctx* ctx, double t);
+
+/* Measurement: average duration in milliseconds of one pass over the state,
+ * launched `reps` times back to back on the context stream between two HIP
+ * events (the state is overwritten with transformed data).  pass: 0 = X-pass
+ * (inverse FFT along x, nonlinear flow, forward FFT; the nonlinear flow of
+ * Sec. 3.2); 1 = y-pass (2D: FFT along y, propagator, inverse FFT; 3D: forward
+ * FFT along y); 2 = z-pass with the propagator (3D); 3 = inverse y-pass (3D).
+ * Requires a built propagator.  Synchronous. */
+int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_ms);
+
+/* Options.  SGP_OPT_GRAPH (default 1): replay the periodic part of sgp_step()
+ * from a captured HIP graph (value 0 launches every kernel individually). */
+enum { SGP_OPT_GRAPH = 1 };
+int sgp_set_option(sgp_ctx* ctx, int option, long value);
 
 /* Release the context (not the caller's workspace or state). */
 void sgp_destroy(sgp_ctx* ctx);

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <complex>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -76,7 +77,6 @@ struct sgp_ctx {
   size_t off_kin[2][3];
   size_t off_clock;
   size_t off_part;
-  int npart = 1024;
 
   int scheme = 0;
   double tau = 0.0;
@@ -85,6 +85,13 @@ struct sgp_ctx {
   bool have_prop = false;
   double t = 0.0;
   std::string err;
+
+  // replay of the periodic part of sgp_step: `gsteps` whole steps captured once
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* gpsi = nullptr;
+  int gsteps = 0;
+  bool use_graph = true;
 
   long npts() const { return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1); }
   void* at(size_t off) const { return ws + off; }
@@ -142,14 +149,16 @@ hipError_t upload_twiddles(sgp_ctx* c) {
   return hipSuccess;
 }
 
-template <typename T>
-hipError_t run_xpass(sgp_ctx* c, int mode, void* psi, double d, int clock_mode, double s_arg) {
-  XArgs a;
-  a.comp_stride = c->npts();
-  a.nlines = (long)c->g.n[1] * (c->g.dim == 3 ? c->g.n[2] : 1);
-  a.ny = c->g.n[1];
-  a.tw_fwd = c->at(c->off_tw[0][0]);
-  a.tw_inv = c->at(c->off_tw[0][1]);
+// Fields shared by every pass of a context.
+PassArgs base_args(const sgp_ctx* c) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
+  a.nlines = (long)ny * nz;
+  a.ny = ny;
+  a.ncols = nx;
+  a.dim = c->g.dim;
+  a.n_q = ny;
   for (int i = 0; i < 3; ++i) {
     bool on = i < c->g.dim;
     a.L[i] = on ? c->g.L[i] : 0.0;
@@ -159,60 +168,69 @@ hipError_t run_xpass(sgp_ctx* c, int mode, void* psi, double d, int clock_mode, 
   a.g2[1] = c->p.gy * c->p.gy;
   a.g2[2] = c->g.dim == 3 ? c->p.gz * c->p.gz : 0.0;
   a.Omega = c->p.Omega;
-  a.d = d;
+  a.gamma = c->p.gamma;
+  a.c0 = c->p.c0;
   a.c0p = c->p.c0 + c->p.c2 / 5.0;
   a.c1 = c->p.c1;
   a.c2 = c->p.c2;
+  a.nu_scale_a = kPi / c->g.L[0];
+  a.nu_scale_q = kPi / c->g.L[1];
+  a.norm = 1.0 / (double)c->npts();
   a.clock = (double*)c->at(c->off_clock);
-  a.s_arg = s_arg;
-  a.clock_mode = clock_mode;
-  long nlines = (long)c->g.n[1] * (c->g.dim == 3 ? c->g.n[2] : 1);
-  return launch_xpass<T>(mode, psi, a, c->g.n[0], nlines, c->st);
+  (void)nz;
+  return a;
 }
 
-template <typename T>
-hipError_t run_colpass(sgp_ctx* c, int mode, int axis, void* psi, int table, double d) {
-  CArgs a;
+// Column geometry for lines along `axis` (1 = y, 2 = z).
+void column_geometry(const sgp_ctx* c, int axis, PassArgs& a) {
   const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
-  a.comp_stride = c->npts();
-  a.ncols = nx;
-  a.dim = c->g.dim;
-  a.n_q = ny;
   if (axis == 1) {
-    a.stride = nx;
+    a.stride = 5L * nx;
     a.nouter = nz;
-    a.outer_stride = (long)nx * ny;
+    a.outer_stride = 5L * nx * ny;
   } else {
-    a.stride = (long)nx * ny;
+    a.stride = 5L * nx * ny;
     a.nouter = ny;
-    a.outer_stride = nx;
+    a.outer_stride = 5L * nx;
   }
   a.tw_fwd = c->at(c->off_tw[axis][0]);
   a.tw_inv = c->at(c->off_tw[axis][1]);
+  a.nu_scale_l = kPi / c->g.L[axis];
+}
+
+template <typename T>
+hipError_t run_xpass(sgp_ctx* c, hipStream_t st, int mode, void* psi, double d, int clock_mode, double s_arg) {
+  PassArgs a = base_args(c);
+  a.tw_fwd = c->at(c->off_tw[0][0]);
+  a.tw_inv = c->at(c->off_tw[0][1]);
+  a.d = d;
+  a.s_arg = s_arg;
+  a.clock_mode = clock_mode;
+  return launch_pass<T>(mode, psi, a, c->g.n[0], st);
+}
+
+template <typename T>
+hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi, int table, double d) {
+  PassArgs a = base_args(c);
+  column_geometry(c, axis, a);
   a.cs = c->at(c->off_cs[table]);
   a.kin_a = c->at(c->off_kin[table][0]);
   a.kin_o = c->at(c->off_kin[table][1]);
   a.kin_l = c->at(c->off_kin[table][axis]);
-  a.nu_scale_a = kPi / c->g.L[0];
-  a.nu_scale_q = kPi / c->g.L[1];
-  a.Omega = c->p.Omega;
-  a.gamma = c->p.gamma;
-  a.norm = 1.0 / (double)c->npts();
   a.d = d;
-  a.clock = (double*)c->at(c->off_clock);
   a.advance_clock = (mode == C_PROP) ? 1 : 0;
-  return launch_colpass<T>(mode, psi, a, c->g.n[axis], c->st);
+  return launch_pass<T>(mode, psi, a, c->g.n[axis], st);
 }
 
 // One exact linear substep on x-transformed data: 2D Y-pass, 3D Y1 + Z + Y2.
 template <typename T>
-hipError_t run_linear(sgp_ctx* c, void* psi, int table, double d) {
-  if (c->g.dim == 2) return run_colpass<T>(c, C_PROP, 1, psi, table, d);
-  hipError_t e = run_colpass<T>(c, C_FWD, 1, psi, table, d);
+hipError_t run_linear(sgp_ctx* c, hipStream_t st, void* psi, int table, double d) {
+  if (c->g.dim == 2) return run_colpass<T>(c, st, C_PROP, 1, psi, table, d);
+  hipError_t e = run_colpass<T>(c, st, C_FWD, 1, psi, table, d);
   if (e != hipSuccess) return e;
-  e = run_colpass<T>(c, C_PROP, 2, psi, table, d);
+  e = run_colpass<T>(c, st, C_PROP, 2, psi, table, d);
   if (e != hipSuccess) return e;
-  return run_colpass<T>(c, C_INV, 1, psi, table, d);
+  return run_colpass<T>(c, st, C_INV, 1, psi, table, d);
 }
 
 // Substep schedule of nsteps steps with merged adjacent nonlinear substeps:
@@ -241,20 +259,167 @@ void schedule(const sgp_ctx* c, long nsteps, std::vector<double>& nl, std::vecto
   }
 }
 
+// The periodic middle of a call: one whole step that starts after a merged
+// nonlinear substep and ends with the next merged one (all clock reads on device).
+template <typename T>
+hipError_t enqueue_body(sgp_ctx* c, hipStream_t st, void* psi, int nbody) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(c, 2, nl, lin, tab);  // the second step of a two-step schedule is a body step
+  const size_t per = lin.size() / 2;
+  for (int b = 0; b < nbody; ++b)
+    for (size_t k = per; k < 2 * per; ++k) {
+      hipError_t e = run_linear<T>(c, st, psi, tab[k], lin[k]);
+      if (e != hipSuccess) return e;
+      // the body's last nonlinear substep is the merged one (2 a1 tau / tau)
+      const double d = (k + 1 == 2 * per) ? nl[per] : nl[k + 1];
+      e = run_xpass<T>(c, st, X_MID, psi, d, CLOCK_DEVICE, 0.0);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+void drop_graph(sgp_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gpsi = nullptr;
+  c->gsteps = 0;
+}
+
+template <typename T>
+hipError_t get_graph(sgp_ctx* c, void* psi, int gsteps) {
+  if (c->gexec && c->gpsi == psi && c->gsteps == gsteps) return hipSuccess;
+  drop_graph(c);
+  hipError_t e;
+  if (!c->cap) {
+    e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e1 = enqueue_body<T>(c, c->cap, psi, gsteps);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap, &g);
+  if (e1 != hipSuccess) { if (g) hipGraphDestroy(g); return e1; }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) { c->gexec = nullptr; return e; }
+  c->gpsi = psi;
+  c->gsteps = gsteps;
+  return hipSuccess;
+}
+
 template <typename T>
 int step_impl(sgp_ctx* c, void* psi, long nsteps) {
   std::vector<double> nl, lin;
   std::vector<int> tab;
-  schedule(c, nsteps, nl, lin, tab);
-  hipError_t e = run_xpass<T>(c, X_FIRST, psi, nl[0], CLOCK_ARG, c->t);
+  schedule(c, 1, nl, lin, tab);  // a single step: first and last nonlinear substeps unmerged
+  hipError_t e = run_xpass<T>(c, c->st, X_FIRST, psi, nl[0], CLOCK_ARG, c->t);
   if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
+  long nbody = nsteps - 1;
+  const int G = 32;
+  if (c->use_graph && nbody >= G) {
+    e = get_graph<T>(c, psi, G);
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+    for (long i = 0; i < nbody / G; ++i) {
+      e = hipGraphLaunch(c->gexec, c->st);
+      if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    }
+    nbody %= G;
+  }
+  if (nbody > 0) {
+    e = enqueue_body<T>(c, c->st, psi, (int)nbody);
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  }
+  // the last step: its linear substeps, then the unmerged final nonlinear substep
   for (size_t k = 0; k < lin.size(); ++k) {
-    e = run_linear<T>(c, psi, tab[k], lin[k]);
+    e = run_linear<T>(c, c->st, psi, tab[k], lin[k]);
     if (e != hipSuccess) return hip_fail(c, e, "linear pass launch");
-    e = run_xpass<T>(c, k + 1 == lin.size() ? X_LAST : X_MID, psi, nl[k + 1], CLOCK_DEVICE, 0.0);
+    e = run_xpass<T>(c, c->st, k + 1 == lin.size() ? X_LAST : X_MID, psi, nl[k + 1], CLOCK_DEVICE, 0.0);
     if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
   }
   c->t += (double)nsteps * c->tau;
+  return SGP_OK;
+}
+
+// Average duration of one pass launched reps times back to back on the context
+// stream, bracketed by HIP events.  pass: 0 X-pass (mid form), 1 linear pass along
+// y (2D: with the propagator; 3D: forward y), 2 z-pass with the propagator (3D),
+// 3 inverse y-pass (3D).
+template <typename T>
+int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(c, e, "event create");
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, e, "event create"); }
+  e = hipEventRecord(e0, c->st);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    if (pass == 0) e = run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], CLOCK_ARG, c->t);
+    else if (pass == 1) e = run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0);
+    else if (pass == 2) e = run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0);
+    else e = run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "pass timing");
+  *avg_ms = (double)ms / reps;
+  return SGP_OK;
+}
+
+// Observables: one x-line pass (d_x, pointwise terms) and one column pass per other
+// axis; FP64 block partials summed on the host in block order (deterministic).
+long obs_nblocks(const sgp_ctx* c, int axis) {
+  const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
+  const int W = lines_per_block(c->g.n[axis], axis == 0, (int)c->esize);
+  if (axis == 0) return ((long)ny * nz + W - 1) / W;
+  const long nouter = axis == 1 ? nz : ny;
+  return ((nx + W - 1) / W) * nouter;
+}
+
+template <typename T>
+int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
+  double* part = (double*)c->at(c->off_part);
+  double tot[3][NOBS];
+  for (int axis = 0; axis < c->g.dim; ++axis) {
+    PassArgs a = base_args(c);
+    if (axis == 0) {
+      a.tw_fwd = c->at(c->off_tw[0][0]);
+      a.tw_inv = c->at(c->off_tw[0][1]);
+      a.nu_scale_l = kPi / c->g.L[0];
+    } else {
+      column_geometry(c, axis, a);
+    }
+    a.s_arg = c->t;
+    const int kind = axis == 0 ? OBS_X : (axis == 1 ? OBS_Y : OBS_Z);
+    hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], part, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "observables launch");
+    const long nb = obs_nblocks(c, axis);
+    std::vector<double> host((size_t)nb * NOBS);
+    e = hipMemcpyAsync(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "observables readback");
+    for (int q = 0; q < NOBS; ++q) {
+      double s = 0.0;
+      for (long b = 0; b < nb; ++b) s += host[(size_t)b * NOBS + q];
+      tot[axis][q] = s;
+    }
+  }
+  double hd = 1.0;
+  for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
+  double ekin = 0.0, lz = 0.0, soc = 0.0;
+  for (int axis = 0; axis < c->g.dim; ++axis) ekin += tot[axis][4];
+  lz = tot[0][5] + tot[1][5];
+  soc = tot[0][6] + tot[1][6];
+  out[0] = hd * tot[0][0];
+  out[2] = hd * tot[0][1];
+  out[3] = hd * lz;
+  out[1] = hd * (ekin + tot[0][2] + tot[0][3] - c->p.gamma * soc) - c->p.Omega * out[3];
   return SGP_OK;
 }
 
@@ -303,7 +468,9 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   c->off_clock = off;
   off += 256;
   c->off_part = off;
-  off += align256(sizeof(double) * 8 * c->npart);
+  long maxb = 0;
+  for (int axis = 0; axis < c->g.dim; ++axis) maxb = std::max(maxb, obs_nblocks(c, axis));
+  off += align256(sizeof(double) * NOBS * maxb);
   c->total = off;
   *out = c;
   return SGP_OK;
@@ -322,6 +489,7 @@ int sgp_set_workspace(sgp_ctx* c, void* dev_ptr, size_t bytes) {
   c->ws = (char*)dev_ptr;
   c->ws_bytes = bytes;
   c->have_prop = false;
+  drop_graph(c);
   hipError_t e = c->dtype == SGP_C64 ? upload_twiddles<float>(c) : upload_twiddles<double>(c);
   if (e != hipSuccess) return hip_fail(c, e, "twiddle upload");
   return SGP_OK;
@@ -332,6 +500,7 @@ int sgp_build_propagator(sgp_ctx* c, double tau, int scheme) {
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!std::isfinite(tau) || tau == 0.0) return fail(c, SGP_ERR_ARG, "tau must be finite and nonzero");
   if (scheme != SGP_TS2 && scheme != SGP_TS4) return fail(c, SGP_ERR_ARG, "scheme must be SGP_TS2 or SGP_TS4");
+  drop_graph(c);
   c->scheme = scheme;
   c->tau = tau;
   if (scheme == SGP_TS2) {
@@ -373,23 +542,7 @@ int sgp_step(sgp_ctx* c, void* psi, long nsteps) {
 int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
-  double* part = (double*)c->at(c->off_part);
-  hipError_t e = c->dtype == SGP_C64 ? launch_mass_magn<float>(psi, c->npts(), part, c->npart, c->st)
-                                     : launch_mass_magn<double>(psi, c->npts(), part, c->npart, c->st);
-  if (e != hipSuccess) return hip_fail(c, e, "observables launch");
-  std::vector<double> host(2 * c->npart);
-  e = hipMemcpyAsync(host.data(), part, sizeof(double) * 2 * c->npart, hipMemcpyDeviceToHost, c->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) return hip_fail(c, e, "observables readback");
-  double m = 0, mg = 0;
-  for (int i = 0; i < c->npart; ++i) { m += host[2 * i]; mg += host[2 * i + 1]; }
-  double hd = 1.0;
-  for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
-  out[0] = hd * m;
-  out[1] = NAN;
-  out[2] = hd * mg;
-  out[3] = NAN;
-  return SGP_OK;
+  return c->dtype == SGP_C64 ? observables_impl<float>(c, psi, out) : observables_impl<double>(c, psi, out);
 }
 
 int sgp_get_time(const sgp_ctx* c, double* t) {
@@ -404,7 +557,31 @@ int sgp_set_time(sgp_ctx* c, double t) {
   return SGP_OK;
 }
 
-void sgp_destroy(sgp_ctx* c) { delete c; }
+int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
+  if (!c || !psi || !avg_ms || reps < 1) return fail(c, SGP_ERR_ARG, "bad argument");
+  if (pass < 0 || pass > 3 || (c->g.dim == 2 && pass > 1)) return fail(c, SGP_ERR_ARG, "no such pass");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  return c->dtype == SGP_C64 ? time_pass_impl<float>(c, psi, pass, reps, avg_ms)
+                             : time_pass_impl<double>(c, psi, pass, reps, avg_ms);
+}
+
+int sgp_set_option(sgp_ctx* c, int option, long value) {
+  if (!c) return SGP_ERR_ARG;
+  if (option == SGP_OPT_GRAPH) {
+    c->use_graph = value != 0;
+    if (!c->use_graph) drop_graph(c);
+    return SGP_OK;
+  }
+  return fail(c, SGP_ERR_ARG, "unknown option");
+}
+
+void sgp_destroy(sgp_ctx* c) {
+  if (!c) return;
+  drop_graph(c);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+}
 
 const char* sgp_last_error(const sgp_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 

@@ -1,180 +1,378 @@
 // Split-step kernels for the rotating SOC spin-2 GPE on gfx950.
 //
+// State layout: [nz][ny][nx][5] complex (components innermost).
+//
 // One linear substep of the compact splitting (Sec. 3.1) in 2D is two passes over
 // the state; each pass reads and writes every value once:
-//   X-pass (rows):    inverse FFT along x, exact nonlinear flow per point (Sec. 3.2)
-//                     with the trap at R(Omega s) x, forward FFT along x.
-//   Y-pass (columns): forward FFT along y, exact linear propagator per wavevector
-//                     (eq. sl1), inverse FFT along y.
+//   X-pass (lines along x): inverse FFT along x, exact nonlinear flow per point
+//                           (Sec. 3.2) with the trap at R(Omega s) x, forward FFT.
+//   Y-pass (lines along y): forward FFT along y, exact linear propagator per
+//                           wavevector (eq. sl1), inverse FFT along y.
 // Between passes the state is held x-transformed (Fourier in x, physical in y).
 // The first X-pass of a call starts from physical data (no inverse FFT) and the
-// last one ends in physical data (no forward FFT).  3D adds a Z-pass that carries
-// the propagator (Y1: forward y, Z: forward z + propagator + inverse z, Y2: inverse y).
+// last one ends in physical data (no forward FFT).  3D: Y1 (forward y),
+// Z (forward z, propagator, inverse z), Y2 (inverse y).
+//
+// Work split inside a block: W lines x 5 components; each (line, component) is
+// transformed by TL = N/E threads holding E elements each (register Stockham FFT
+// with LDS exchanges).  The pointwise stage (nonlinear flow or propagator) needs the
+// 5 components of a point together: the block writes its lines into an LDS tile
+// (components innermost), every thread updates whole points from the tile, and
+// the FFT threads read their elements back.
 #include "sgp_device.hpp"
 #include "sgp_kernels.hpp"
 
 namespace sgp {
 
-// ---------------------------------------------------------------------------
-// Rotation angle of the trap: theta = Omega * s with s the device clock (advanced
-// by the linear passes) or a value passed by the host.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void trap_angle(const XArgs& a, double& c, double& s) {
+template <int N> struct PadLine { static constexpr int size = LdsLine<N>::size; };
+
+// Block index -> logical tile index so that the 8 XCDs (which take blocks round
+// robin) each process one contiguous range of tiles and share their L2 lines.
+__device__ __forceinline__ long xcd_tile(long b, long nblocks) {
+  if (nblocks % 8) return b;
+  return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+__device__ __forceinline__ void trap_angle(const PassArgs& a, double& c, double& s) {
   const double clk = a.clock_mode == CLOCK_ARG ? a.s_arg : a.clock[0];
   sincos(a.Omega * clk, &s, &c);
 }
 
 // ---------------------------------------------------------------------------
-// X-pass, 2D or 3D: one line along x per TL = N/E threads, all 5 components.
-// MODE: X_FIRST (physical in -> NL -> FFT), X_MID (iFFT -> NL -> FFT),
-//       X_LAST (iFFT -> NL -> physical out), X_NLONLY (physical -> NL -> physical).
+// Generic pass.  KIND selects the line direction and the stages:
+//   X_FIRST: load phys -> NL -> FFTx -> store       X_MID: iFFTx -> NL -> FFTx
+//   X_LAST:  iFFTx -> NL -> store phys              X_NLONLY: NL only
+//   C_PROP:  FFT -> propagator -> iFFT (column)     C_FWD / C_INV: FFT / iFFT only
 // ---------------------------------------------------------------------------
-template <typename T, int N, int E, int MODE>
-__global__ __launch_bounds__(256) void k_xpass(cx<T>* __restrict__ psi, XArgs a) {
+template <typename T, int N, int E, int W, int KIND>
+__global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ psi, PassArgs a) {
   constexpr int TL = N / E;
-  constexpr int LPB = 256 / TL;  // lines per block
-  constexpr int LS = LdsLine<N>::size;
-  __shared__ T lre[LPB * LS];
-  __shared__ T lim[LPB * LS];
+  constexpr int NT = W * 5 * TL;
+  constexpr int LS = PadLine<N>::size;
+  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY;
+  constexpr bool PW = XL || KIND == C_PROP;  // has a pointwise stage
+  constexpr int TILE = PW ? W * N * 5 : 0;
+  constexpr int XCH = W * 5 * LS;
+  constexpr int BUF = TILE > XCH ? TILE : XCH;
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+
   const int tid = threadIdx.x;
-  const int lloc = tid / TL, t = tid % TL;
-  const long line = (long)blockIdx.x * LPB + lloc;  // line = z * ny + y
-  // Lines past the end (grids with fewer lines than a block holds) run the
-  // arithmetic on zeros and never touch global memory.
-  const bool active = line < a.nlines;
-  const int iy = (int)(line % a.ny);
-  const int iz = (int)(line / a.ny);
-  cx<T>* base = psi + (active ? line : 0) * N;
-  cx<T> v[5][E];
-#pragma unroll
-  for (int c = 0; c < 5; ++c)
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[c][m] = active ? base[c * a.comp_stride + t + TL * m] : mk<T>(T(0), T(0));
-  T* re = lre + lloc * LS;
-  T* im = lim + lloc * LS;
-  constexpr int SYNC = (TL <= 64) ? 1 : 0;
-  if constexpr (MODE == X_MID || MODE == X_LAST)
-    fft_line<T, N, E, +1, 5, 1, SYNC>(v, re, im, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
-  // nonlinear flow
-  double ct, st;
-  trap_angle(a, ct, st);
-  const double y = -a.L[1] + iy * a.h[1];
-  const double z = -a.L[2] + iz * a.h[2];
-  const double vz = 0.5 * a.g2[2] * z * z;
-  NLCoef K;
-  K.d = a.d;
-  K.c0p = a.c0p;
-  K.c1 = a.c1;
-  K.c2 = a.c2;
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const double x = -a.L[0] + (t + TL * m) * a.h[0];
-    const double X = ct * x + st * y, Y = -st * x + ct * y;
-    const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y) + vz;
-    cx<T> p[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) p[c] = v[c][m];
-    nl_point<T>(p, V, K);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) v[c][m] = p[c];
+  const int c = tid % 5;
+  const int rest = tid / 5;
+  // x-lines: the TL threads of a line are adjacent (contiguous loads);
+  // columns: the W columns are adjacent (W*5 contiguous values per row)
+  const int col = XL ? rest / TL : rest % W;
+  const int t = XL ? rest % TL : rest / W;
+  const long tile = xcd_tile(blockIdx.x, gridDim.x);
+
+  // line geometry
+  long base;        // element offset of the line's first point (component 0)
+  long estride;     // element stride between consecutive points of the line
+  long line0 = 0;   // x-lines: first line of the block (line = z * ny + y)
+  long o = 0, kx0 = 0;
+  bool active;
+  if constexpr (XL) {
+    line0 = tile * W;
+    const long line = line0 + col;
+    active = line < a.nlines;
+    base = (active ? line : 0) * (long)N * 5;
+    estride = 5;
+  } else {
+    const long ncolblk = (a.ncols + W - 1) / W;
+    o = tile / ncolblk;
+    kx0 = (tile % ncolblk) * W;
+    const long kx = kx0 + col;
+    active = kx < a.ncols;
+    base = o * a.outer_stride + (active ? kx : 0) * 5;
+    estride = a.stride;
   }
-  if constexpr (MODE == X_FIRST || MODE == X_MID)
-    fft_line<T, N, E, -1, 5, 1, SYNC>(v, re, im, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
+
+  cx<T> v[1][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
+
+  T* xre = lre + (col * 5 + c) * LS;
+  T* xim = lim + (col * 5 + c) * LS;
+  const cx<T>* twf = reinterpret_cast<const cx<T>*>(a.tw_fwd);
+  const cx<T>* twi = reinterpret_cast<const cx<T>*>(a.tw_inv);
+
+  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+  if constexpr (KIND == C_PROP || KIND == C_FWD) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+
+  if constexpr (PW) {
+    // to the tile: point (col, j) component c at (col * N + j) * 5 + c
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int o5 = (col * N + t + TL * m) * 5 + c;
+      lre[o5] = v[0][m].re;
+      lim[o5] = v[0][m].im;
+    }
+    __syncthreads();
+    if constexpr (XL) {
+      NLCoef K;
+      K.d = a.d;
+      K.c0p = a.c0p;
+      K.c1 = a.c1;
+      K.c2 = a.c2;
+      double ct, st;
+      trap_angle(a, ct, st);
+      for (int pt = tid; pt < W * N; pt += NT) {
+        const int pc = pt / N, j = pt % N;
+        const long line = line0 + pc;
+        const int iy = (int)(line % a.ny), iz = (int)(line / a.ny);
+        const double x = -a.L[0] + j * a.h[0];
+        const double y = -a.L[1] + iy * a.h[1];
+        const double z = -a.L[2] + iz * a.h[2];
+        const double X = ct * x + st * y, Y = -st * x + ct * y;
+        const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y + a.g2[2] * z * z);
+        cx<T> p[5];
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) p[cc] = mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
+        nl_point<T>(p, V, K);
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+      }
+    } else {
+      const T* cs = reinterpret_cast<const T*>(a.cs);
+      const cx<T>* kin_a = reinterpret_cast<const cx<T>*>(a.kin_a);
+      const cx<T>* kin_o = reinterpret_cast<const cx<T>*>(a.kin_o);
+      const cx<T>* kin_l = reinterpret_cast<const cx<T>*>(a.kin_l);
+      const T Om = T(a.Omega), ga = T(a.gamma), norm = T(a.norm);
+      const int nxx = (int)a.ncols;
+      for (int pt = tid; pt < W * N; pt += NT) {
+        const int pc = pt / N, kl = pt % N;
+        const long kx = kx0 + pc < a.ncols ? kx0 + pc : 0;
+        const int px = (int)(kx < nxx / 2 ? kx : kx - nxx);
+        const T nup = T(px * a.nu_scale_a);
+        int kq;
+        long qidx;
+        cx<T> ka = kin_a[kx];
+        if (a.dim == 2) {
+          kq = kl;
+          qidx = (long)kl * nxx + kx;
+        } else {
+          kq = (int)o;
+          qidx = o * nxx + kx;
+          const cx<T> ko = kin_o[o];
+          ka = ka + ko + ka * ko;
+        }
+        const int pq = kq < a.n_q / 2 ? kq : kq - a.n_q;
+        const T nuq = T(pq * a.nu_scale_q);
+        const T Cm1 = cs[2 * qidx], S = cs[2 * qidx + 1];
+        // alpha - 1 = (C - 1) - i S Omega; beta = i S gamma a = S gamma (nu_p - i nu_q)
+        const cx<T> as = mk<T>(Cm1, -S * Om);
+        const cx<T> beta = mk<T>(S * ga * nup, -S * ga * nuq);
+        const cx<T> kl1 = kin_l[kl];
+        const cx<T> ss = ka + kl1 + ka * kl1;  // kinetic phase - 1
+        cx<T> p[5];
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) p[cc] = norm * mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
+        sym4_apply_inc<T>(as, beta, ss, p);
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int o5 = (col * N + t + TL * m) * 5 + c;
+      v[0][m] = mk<T>(lre[o5], lim[o5]);
+    }
+    __syncthreads();
+  }
+
+  if constexpr (KIND == X_FIRST || KIND == X_MID) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+  if constexpr (KIND == C_PROP) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
-#pragma unroll
-      for (int m = 0; m < E; ++m) base[c * a.comp_stride + t + TL * m] = v[c][m];
+    for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
   }
-  if (a.clock_mode == CLOCK_ARG && blockIdx.x == 0 && tid == 0) a.clock[0] = a.s_arg;
+  if constexpr (XL) {
+    if (a.clock_mode == CLOCK_ARG && blockIdx.x == 0 && tid == 0) a.clock[0] = a.s_arg;
+  }
+  if constexpr (KIND == C_PROP) {
+    if (a.advance_clock && blockIdx.x == 0 && tid == 0) a.clock[0] += a.d;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Column pass: lines of length N with element stride `stride` (nx for y-lines,
-// nx*ny for z-lines), W adjacent lines per block (coalesced W-wide segments).
-// MODE: C_PROP (FFT -> propagator -> iFFT, the last-axis pass), C_FWD (FFT only),
-//       C_INV (iFFT only).
-// The propagator at wavevector (p, q[, r]) is exp(-i d |nu|^2/2) exp(i d Q) applied
-// as sym4 of U = [[C - i S Omega, i S gamma a], [i S gamma conj(a), C + i S Omega]],
-// a = -nu_q - i nu_p, C = cos(lam d/2), S = sin(lam d/2)/lam (table), times the
-// kinetic phase from per-axis tables and the 1/N^d scale of the forward transform.
+// Observables (Sec. 2) on the physical state, FP64 partial sums per block.
+// OBS_X (lines along x): d_x psi spectrally; per point the mass, the
+//   magnetization, V|psi|^2, the interaction energy, |d_x psi|^2/2,
+//   Re(conj(psi) i y d_x psi) (the y d_x part of -i(x d_y - y d_x)) and
+//   Re(psi^H K d_x psi);
+// OBS_Y / OBS_Z (columns): d_y psi (or d_z psi); |d psi|^2/2,
+//   Re(conj(psi) (-i x) d_y psi) and Re(i psi^H M d_y psi) (y only).
+// With L+- = i d_y +- d_x the SOC matrix is S = i d_y M + d_x K, M symmetric with
+// the weights (1, sqrt6/2, sqrt6/2, 1) on both off-diagonals, K = -M above and +M
+// below the diagonal.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int E, int W, int MODE>
-__global__ __launch_bounds__(W * (N / E)) void k_colpass(cx<T>* __restrict__ psi, CArgs a) {
-  constexpr int TC = N / E;
-  constexpr int CS = LdsLine<N>::size + 1;  // odd column stride in LDS
-  __shared__ T lre[W * CS];
-  __shared__ T lim[W * CS];
+template <typename T, int N, int E, int W, int KIND>
+__global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict__ psi, PassArgs a,
+                                                         double* __restrict__ part) {
+  constexpr int TL = N / E;
+  constexpr int NT = W * 5 * TL;
+  constexpr int LS = PadLine<N>::size;
+  constexpr bool XL = KIND == OBS_X;
+  constexpr int TILE = 2 * W * N * 5;
+  constexpr int XCH = W * 5 * LS;
+  constexpr int BUF = TILE > XCH ? TILE : XCH;
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double red[NT / 64 + 1][NOBS];
+
   const int tid = threadIdx.x;
-  const int col = tid % W, t = tid / W;
-  // block -> (outer index o, first column): columns run along the contiguous axis
-  const long ncolblk = (a.ncols + W - 1) / W;
-  const long o = blockIdx.x / ncolblk;
-  const long kx0 = (blockIdx.x % ncolblk) * W + col;  // index along the contiguous axis
-  // Columns past the end (ncols < W) compute on zeros and never touch global memory.
-  const bool active = kx0 < a.ncols;
-  const long kx = active ? kx0 : 0;
-  cx<T>* base = psi + o * a.outer_stride + kx;
-  cx<T> v[5][E];
+  const int c = tid % 5;
+  const int rest = tid / 5;
+  const int col = XL ? rest / TL : rest % W;
+  const int t = XL ? rest % TL : rest / W;
+  const long tile = blockIdx.x;
+  long base, estride, line0 = 0, o = 0, kx0 = 0;
+  bool active;
+  if constexpr (XL) {
+    line0 = tile * W;
+    const long line = line0 + col;
+    active = line < a.nlines;
+    base = (active ? line : 0) * (long)N * 5;
+    estride = 5;
+  } else {
+    const long ncolblk = (a.ncols + W - 1) / W;
+    o = tile / ncolblk;
+    kx0 = (tile % ncolblk) * W;
+    const long kx = kx0 + col;
+    active = kx < a.ncols;
+    base = o * a.outer_stride + (active ? kx : 0) * 5;
+    estride = a.stride;
+  }
+  cx<T> v[1][E], f[E];
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
+  for (int m = 0; m < E; ++m) {
+    v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
+    f[m] = v[0][m];
+  }
+  T* xre = lre + (col * 5 + c) * LS;
+  T* xim = lim + (col * 5 + c) * LS;
+  // derivative along the line: FFT, multiply by i nu / N, inverse FFT
+  fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-      v[c][m] = active ? base[c * a.comp_stride + (long)(t + TC * m) * a.stride] : mk<T>(T(0), T(0));
-  T* re = lre + col * CS;
-  T* im = lim + col * CS;
-  if constexpr (MODE == C_PROP || MODE == C_FWD)
-    fft_line<T, N, E, -1, 5, 1, 0>(v, re, im, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
-  if constexpr (MODE == C_PROP) {
-    const T* cs = reinterpret_cast<const T*>(a.cs);
-    const cx<T>* kin_a = reinterpret_cast<const cx<T>*>(a.kin_a);  // along the contiguous axis
-    const cx<T>* kin_o = reinterpret_cast<const cx<T>*>(a.kin_o);  // along the outer axis (3D: y)
-    const cx<T>* kin_l = reinterpret_cast<const cx<T>*>(a.kin_l);  // along this pass's axis
-    const T Om = T(a.Omega), ga = T(a.gamma);
-    const T norm = T(a.norm);  // 1/N^d, a power of two: exact
-    const int nxx = (int)a.ncols;
-    const int px = (int)(kx < nxx / 2 ? kx : kx - nxx);
-    const T nup = T(px * a.nu_scale_a);
-    cx<T> ka = kin_a[kx];
-    if (a.dim == 3) {
-      const cx<T> ko = kin_o[o];
-      ka = ka + ko + ka * ko;
+  for (int m = 0; m < E; ++m) {
+    const int k = t + TL * m;
+    const int p = k < N / 2 ? k : k - N;
+    const T nu = T(p * a.nu_scale_l / N);
+    v[0][m] = mk<T>(-nu * v[0][m].im, nu * v[0][m].re);
+  }
+  fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
+  // tile: psi at [0, W N 5), derivative at [W N 5, 2 W N 5)
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int o5 = (col * N + t + TL * m) * 5 + c;
+    lre[o5] = f[m].re;
+    lim[o5] = f[m].im;
+    lre[W * N * 5 + o5] = v[0][m].re;
+    lim[W * N * 5 + o5] = v[0][m].im;
+  }
+  __syncthreads();
+  double acc[NOBS];
+#pragma unroll
+  for (int q = 0; q < NOBS; ++q) acc[q] = 0.0;
+  const double h6 = 1.22474487139158904909864203735294570;
+  const double w[4] = {1.0, h6, h6, 1.0};  // weights of the links (l, l-1), l = 2..-1
+  double ct = 1.0, st = 0.0;
+  if constexpr (XL) sincos(a.Omega * a.s_arg, &st, &ct);
+  for (int pt = tid; pt < W * N; pt += NT) {
+    const int pc = pt / N, j = pt % N;
+    bool on;
+    double x, y, z;
+    if constexpr (XL) {
+      const long line = line0 + pc;
+      on = line < a.nlines;
+      const int iy = (int)(line % a.ny), iz = (int)(line / a.ny);
+      x = -a.L[0] + j * a.h[0];
+      y = -a.L[1] + iy * a.h[1];
+      z = -a.L[2] + iz * a.h[2];
+    } else {
+      on = kx0 + pc < a.ncols;
+      x = -a.L[0] + (kx0 + pc) * a.h[0];
+      y = z = 0.0;
     }
+    if (!on) continue;
+    double pr[5], pi[5], dr[5], di[5];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int kl = t + TC * m;
-      // 2D: the line runs along y = q; 3D: along z, with q the outer index
-      long qidx;
-      int kq;
-      if (a.dim == 2) { kq = kl; qidx = (long)kl * nxx + kx; }
-      else { kq = (int)o; qidx = o * nxx + kx; }
-      const int pq = kq < a.n_q / 2 ? kq : kq - a.n_q;
-      const T nuq = T(pq * a.nu_scale_q);
-      const T Cm1 = cs[2 * qidx], S = cs[2 * qidx + 1];
-      // alpha - 1 = (C - 1) - i S Omega
-      const cx<T> as = mk<T>(Cm1, -S * Om);
-      // beta = i S gamma a, a = -nu_q - i nu_p  ->  S gamma (nu_p - i nu_q)
-      const cx<T> beta = mk<T>(S * ga * nup, -S * ga * nuq);
-      // kinetic phase - 1: (1 + ka)(1 + kl) - 1
-      const cx<T> kl1 = kin_l[kl];
-      const cx<T> ss = ka + kl1 + ka * kl1;
-      cx<T> x[5];
+    for (int cc = 0; cc < 5; ++cc) {
+      pr[cc] = lre[pt * 5 + cc];
+      pi[cc] = lim[pt * 5 + cc];
+      dr[cc] = lre[W * N * 5 + pt * 5 + cc];
+      di[cc] = lim[W * N * 5 + pt * 5 + cc];
+    }
+    double grad2 = 0.0, rot = 0.0;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) x[c] = norm * v[c][m];
-      sym4_apply_inc<T>(as, beta, ss, x);
+    for (int cc = 0; cc < 5; ++cc) {
+      grad2 += dr[cc] * dr[cc] + di[cc] * di[cc];
+      rot += pr[cc] * di[cc] - pi[cc] * dr[cc];  // Im(conj(psi) d psi)
+    }
+    if constexpr (XL) {
+      double n[5], rho = 0.0;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) v[c][m] = x[c];
+      for (int cc = 0; cc < 5; ++cc) { n[cc] = pr[cc] * pr[cc] + pi[cc] * pi[cc]; rho += n[cc]; }
+      const double mg = 2.0 * (n[0] - n[4]) + (n[1] - n[3]);
+      const double X = ct * x + st * y, Y = -st * x + ct * y;
+      const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y + a.g2[2] * z * z);
+      // F_+ = 2 (conj(p2) p1 + conj(p-1) p-2) + sqrt6 (conj(p1) p0 + conj(p0) p-1)
+      double fr = 0.0, fi = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        fr += 2.0 * w[l] * (pr[l] * pr[l + 1] + pi[l] * pi[l + 1]);
+        fi += 2.0 * w[l] * (pr[l] * pi[l + 1] - pi[l] * pr[l + 1]);
+      }
+      // A00 = (2 p2 p-2 - 2 p1 p-1 + p0^2)/sqrt5
+      const double ar = (2.0 * (pr[0] * pr[4] - pi[0] * pi[4]) - 2.0 * (pr[1] * pr[3] - pi[1] * pi[3]) +
+                         (pr[2] * pr[2] - pi[2] * pi[2])) * 0.44721359549995793928;
+      const double ai = (2.0 * (pr[0] * pi[4] + pi[0] * pr[4]) - 2.0 * (pr[1] * pi[3] + pi[1] * pr[3]) +
+                         2.0 * pr[2] * pi[2]) * 0.44721359549995793928;
+      const double eint = 0.5 * a.c0 * rho * rho + 0.5 * a.c1 * (fr * fr + fi * fi + mg * mg) +
+                          0.5 * a.c2 * (ar * ar + ai * ai);
+      // Re psi^H K d_x psi: -w conj(p_l) d p_(l+1) + w conj(p_(l+1)) d p_l
+      double soc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        soc += w[l] * (-(pr[l] * dr[l + 1] + pi[l] * di[l + 1]) + (pr[l + 1] * dr[l] + pi[l + 1] * di[l]));
+      acc[0] += rho;
+      acc[1] += mg;
+      acc[2] += V * rho;
+      acc[3] += eint;
+      acc[4] += 0.5 * grad2;
+      acc[5] += -y * rot;  // Re(conj(psi) (i y) d_x psi)
+      acc[6] += soc;
+    } else {
+      acc[4] += 0.5 * grad2;
+      if constexpr (KIND == OBS_Y) {
+        acc[5] += x * rot;  // Re(conj(psi) (-i x) d_y psi)
+        // Re(i psi^H M d_y psi) = -Im(psi^H M d_y psi)
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+          s += w[l] * ((pr[l] * di[l + 1] - pi[l] * dr[l + 1]) + (pr[l + 1] * di[l] - pi[l + 1] * dr[l]));
+        acc[6] += -s;
+      }
     }
   }
-  if constexpr (MODE == C_PROP || MODE == C_INV)
-    fft_line<T, N, E, +1, 5, 1, 0>(v, re, im, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
-  if (active) {
+  // block reduction in a fixed order
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
+  for (int q = 0; q < NOBS; ++q) {
+    double vq = acc[q];
 #pragma unroll
-      for (int m = 0; m < E; ++m) base[c * a.comp_stride + (long)(t + TC * m) * a.stride] = v[c][m];
+    for (int off = 32; off > 0; off >>= 1) vq += __shfl_down(vq, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6][q] = vq;
   }
-  if (MODE == C_PROP && a.advance_clock && blockIdx.x == 0 && tid == 0) a.clock[0] += a.d;
+  __syncthreads();
+  if (tid < NOBS) {
+    double s = 0.0;
+    for (int wv = 0; wv < (NT + 63) / 64; ++wv) s += red[wv][tid];
+    part[(long)blockIdx.x * NOBS + tid] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -221,93 +419,93 @@ __global__ void k_build_kin(cx<T>* __restrict__ kin, int n, double L, double d) 
 }
 
 // ---------------------------------------------------------------------------
-// Mass and magnetization partial sums, FP64: one partial per block, summed in a
-// fixed order by the host (deterministic).
+// Launchers.  Lines per block W: x-lines fill at least 256 threads; columns take 2
+// (complex64) or 1 (complex128) adjacent columns (80 contiguous bytes per row)
+// unless the lines are short.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_mass_magn(const cx<T>* __restrict__ psi, long npts, double* __restrict__ part) {
-  double m = 0.0, mg = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (long)gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const cx<T> z = psi[c * npts + i];
-      const double n = (double)z.re * z.re + (double)z.im * z.im;
-      m += n;
-      mg += (2 - c) * n;
-    }
-  }
-  // wavefront reduction, then across the 4 wavefronts of the block
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    m += __shfl_down(m, off, 64);
-    mg += __shfl_down(mg, off, 64);
-  }
-  __shared__ double sm[2][4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) { sm[0][wv] = m; sm[1][wv] = mg; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sm[0][0] + sm[0][1] + sm[0][2] + sm[0][3];
-    part[2 * blockIdx.x + 1] = sm[1][0] + sm[1][1] + sm[1][2] + sm[1][3];
-  }
+template <typename T, int N>
+struct Geo {
+  static constexpr int E = 8;
+  static constexpr int TL = N / E;
+  static constexpr int WX = (5 * TL >= 256) ? 1 : (256 + 5 * TL - 1) / (5 * TL);
+  static constexpr int WC = (5 * TL >= 256) ? (sizeof(T) == 4 ? 2 : 1) : (256 + 5 * TL - 1) / (5 * TL);
+};
+
+int lines_per_block(int n, bool xline, int esize) {
+  const int TL = n / 8;
+  if (5 * TL >= 256) return xline ? 1 : (esize == 4 ? 2 : 1);
+  return (256 + 5 * TL - 1) / (5 * TL);
 }
 
-// ---------------------------------------------------------------------------
-// Launchers
-// ---------------------------------------------------------------------------
-template <typename T, int N, int E>
-static hipError_t xpass_n(int mode, cx<T>* psi, const XArgs& a, long nlines, hipStream_t st) {
-  constexpr int TL = N / E;
-  constexpr int LPB = 256 / TL;
-  if (nlines != a.nlines) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((nlines + LPB - 1) / LPB)), block(256);
-  switch (mode) {
-    case X_FIRST: hipLaunchKernelGGL((k_xpass<T, N, E, X_FIRST>), grid, block, 0, st, psi, a); break;
-    case X_MID: hipLaunchKernelGGL((k_xpass<T, N, E, X_MID>), grid, block, 0, st, psi, a); break;
-    case X_LAST: hipLaunchKernelGGL((k_xpass<T, N, E, X_LAST>), grid, block, 0, st, psi, a); break;
-    default: hipLaunchKernelGGL((k_xpass<T, N, E, X_NLONLY>), grid, block, 0, st, psi, a); break;
-  }
+template <typename T, int N, int KIND>
+static hipError_t pass_n(cx<T>* psi, const PassArgs& a, hipStream_t st) {
+  constexpr int E = Geo<T, N>::E;
+  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY;
+  constexpr int W = XL ? Geo<T, N>::WX : Geo<T, N>::WC;
+  constexpr int NT = W * 5 * (N / E);
+  long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
+  hipLaunchKernelGGL((k_pass<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(NT), 0, st, psi, a);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_xpass(int mode, void* psi, const XArgs& a, int nx, long nlines, hipStream_t st) {
-  cx<T>* p = reinterpret_cast<cx<T>*>(psi);
-  switch (nx) {
-    case 16: return xpass_n<T, 16, 8>(mode, p, a, nlines, st);
-    case 32: return xpass_n<T, 32, 8>(mode, p, a, nlines, st);
-    case 64: return xpass_n<T, 64, 8>(mode, p, a, nlines, st);
-    case 128: return xpass_n<T, 128, 8>(mode, p, a, nlines, st);
-    case 256: return xpass_n<T, 256, 8>(mode, p, a, nlines, st);
-    case 512: return xpass_n<T, 512, 8>(mode, p, a, nlines, st);
+template <typename T, int N>
+static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t st) {
+  switch (kind) {
+    case X_FIRST: return pass_n<T, N, X_FIRST>(psi, a, st);
+    case X_MID: return pass_n<T, N, X_MID>(psi, a, st);
+    case X_LAST: return pass_n<T, N, X_LAST>(psi, a, st);
+    case X_NLONLY: return pass_n<T, N, X_NLONLY>(psi, a, st);
+    case C_PROP: return pass_n<T, N, C_PROP>(psi, a, st);
+    case C_FWD: return pass_n<T, N, C_FWD>(psi, a, st);
+    case C_INV: return pass_n<T, N, C_INV>(psi, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, int N, int E>
-static hipError_t colpass_n(int mode, cx<T>* psi, const CArgs& a, hipStream_t st) {
-  constexpr int TC = N / E;
-  constexpr int W0 = (sizeof(T) == 4 ? 8 : 4);
-  constexpr int W = (256 / TC > W0) ? 256 / TC : W0;
-  dim3 grid((unsigned)(((a.ncols + W - 1) / W) * a.nouter)), block(W * TC);
-  switch (mode) {
-    case C_PROP: hipLaunchKernelGGL((k_colpass<T, N, E, W, C_PROP>), grid, block, 0, st, psi, a); break;
-    case C_FWD: hipLaunchKernelGGL((k_colpass<T, N, E, W, C_FWD>), grid, block, 0, st, psi, a); break;
-    default: hipLaunchKernelGGL((k_colpass<T, N, E, W, C_INV>), grid, block, 0, st, psi, a); break;
+template <typename T>
+hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, hipStream_t st) {
+  cx<T>* p = reinterpret_cast<cx<T>*>(psi);
+  switch (n) {
+    case 16: return pass_kind<T, 16>(kind, p, a, st);
+    case 32: return pass_kind<T, 32>(kind, p, a, st);
+    case 64: return pass_kind<T, 64>(kind, p, a, st);
+    case 128: return pass_kind<T, 128>(kind, p, a, st);
+    case 256: return pass_kind<T, 256>(kind, p, a, st);
+    case 512: return pass_kind<T, 512>(kind, p, a, st);
+    default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int N, int KIND>
+static hipError_t obs_n(const cx<T>* psi, const PassArgs& a, double* part, hipStream_t st) {
+  constexpr int E = Geo<T, N>::E;
+  constexpr bool XL = KIND == OBS_X;
+  constexpr int W = XL ? Geo<T, N>::WX : Geo<T, N>::WC;
+  constexpr int NT = W * 5 * (N / E);
+  long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
+  hipLaunchKernelGGL((k_obs<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(NT), 0, st, psi, a, part);
   return hipGetLastError();
 }
 
+template <typename T, int N>
+static hipError_t obs_kind(int kind, const cx<T>* psi, const PassArgs& a, double* part, hipStream_t st) {
+  switch (kind) {
+    case OBS_X: return obs_n<T, N, OBS_X>(psi, a, part, st);
+    case OBS_Y: return obs_n<T, N, OBS_Y>(psi, a, part, st);
+    default: return obs_n<T, N, OBS_Z>(psi, a, part, st);
+  }
+}
+
 template <typename T>
-hipError_t launch_colpass(int mode, void* psi, const CArgs& a, int n, hipStream_t st) {
-  cx<T>* p = reinterpret_cast<cx<T>*>(psi);
+hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, double* part, hipStream_t st) {
+  const cx<T>* p = reinterpret_cast<const cx<T>*>(psi);
   switch (n) {
-    case 16: return colpass_n<T, 16, 8>(mode, p, a, st);
-    case 32: return colpass_n<T, 32, 8>(mode, p, a, st);
-    case 64: return colpass_n<T, 64, 8>(mode, p, a, st);
-    case 128: return colpass_n<T, 128, 8>(mode, p, a, st);
-    case 256: return colpass_n<T, 256, 8>(mode, p, a, st);
-    case 512: return colpass_n<T, 512, 8>(mode, p, a, st);
+    case 16: return obs_kind<T, 16>(kind, p, a, part, st);
+    case 32: return obs_kind<T, 32>(kind, p, a, part, st);
+    case 64: return obs_kind<T, 64>(kind, p, a, part, st);
+    case 128: return obs_kind<T, 128>(kind, p, a, part, st);
+    case 256: return obs_kind<T, 256>(kind, p, a, part, st);
+    case 512: return obs_kind<T, 512>(kind, p, a, part, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -325,21 +523,13 @@ hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_mass_magn(const void* psi, long npts, double* part, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_mass_magn<T>), dim3(nblocks), dim3(256), 0, st, (const cx<T>*)psi, npts, part);
-  return hipGetLastError();
-}
-
-template hipError_t launch_xpass<float>(int, void*, const XArgs&, int, long, hipStream_t);
-template hipError_t launch_xpass<double>(int, void*, const XArgs&, int, long, hipStream_t);
-template hipError_t launch_colpass<float>(int, void*, const CArgs&, int, hipStream_t);
-template hipError_t launch_colpass<double>(int, void*, const CArgs&, int, hipStream_t);
+template hipError_t launch_pass<float>(int, void*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_pass<double>(int, void*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_obs<float>(int, const void*, const PassArgs&, int, double*, hipStream_t);
+template hipError_t launch_obs<double>(int, const void*, const PassArgs&, int, double*, hipStream_t);
 template hipError_t launch_build_tables<float>(void*, void*, void*, void*, const int*, const double*, int, double,
                                                double, double, hipStream_t);
 template hipError_t launch_build_tables<double>(void*, void*, void*, void*, const int*, const double*, int, double,
                                                 double, double, hipStream_t);
-template hipError_t launch_mass_magn<float>(const void*, long, double*, int, hipStream_t);
-template hipError_t launch_mass_magn<double>(const void*, long, double*, int, hipStream_t);
 
 }  // namespace sgp

@@ -4,8 +4,9 @@ Every numerical step runs in the HIP library libsgp.so; this module only loads i
 converts torch tensors to device pointers and turns error codes into exceptions.
 PyTorch provides device memory (state and workspace tensors) and the stream.
 
-State tensors: torch.complex64 or torch.complex128, shape (5, ny, nx) or
-(5, nz, ny, nx), contiguous, on a ROCm device; component i <-> l = 2, 1, 0, -1, -2.
+State tensors: torch.complex64 or torch.complex128, shape (ny, nx, 5) or
+(nz, ny, nx, 5) (the 5 components of a grid point adjacent), contiguous, on a
+ROCm device; component i <-> l = 2, 1, 0, -1, -2.
 """
 import ctypes
 import os
@@ -18,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsgp.so")
 SGP_OK = 0
 SGP_C64, SGP_C128 = 0, 1
 SGP_TS2, SGP_TS4 = 2, 4
+SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
 
 
 class SgpError(RuntimeError):
@@ -53,6 +55,8 @@ def lib():
     L.sgp_observables.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     L.sgp_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.sgp_set_time.argtypes = [vp, ctypes.c_double]
+    L.sgp_time_pass.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.sgp_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_long]
     L.sgp_destroy.argtypes = [vp]
     L.sgp_destroy.restype = None
     L.sgp_last_error.argtypes = [vp]
@@ -64,7 +68,8 @@ def lib():
 def exported_symbols():
     """Names of the C-ABI entry points this binding expects (all declared in sgp.h)."""
     return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
-            "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_destroy", "sgp_last_error"]
+            "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
+            "sgp_last_error"]
 
 
 def _check(rc, ctx=None):
@@ -85,6 +90,18 @@ class Solver:
     shape: spatial shape (ny, nx) or (nz, ny, nx); L: half-width (scalar or per
     axis in x, y, z order); params: (c0, c1, c2, Omega, gamma, gx, gy, gz).
     """
+
+    @staticmethod
+    def to_device_layout(psi_cfirst):
+        """(5, ..., nx) component-first array -> (..., nx, 5) layout of the library."""
+        import numpy as np
+        return np.ascontiguousarray(np.moveaxis(np.asarray(psi_cfirst), 0, -1))
+
+    @staticmethod
+    def from_device_layout(psi_clast):
+        """(..., nx, 5) -> (5, ..., nx)."""
+        import numpy as np
+        return np.ascontiguousarray(np.moveaxis(np.asarray(psi_clast), -1, 0))
 
     def __init__(self, shape, L, params, dtype="complex64", device="cuda:0", stream=None):
         import torch
@@ -114,8 +131,8 @@ class Solver:
         _check(lib().sgp_set_workspace(ctx, ctypes.c_void_p(self.workspace.data_ptr()), nb.value), ctx)
 
     def _psi_ptr(self, psi):
-        if psi.dtype != self.torch_dtype or tuple(psi.shape) != (5,) + self.shape:
-            raise SgpError(f"state must be {self.torch_dtype} of shape {(5,) + self.shape}, got {psi.dtype} "
+        if psi.dtype != self.torch_dtype or tuple(psi.shape) != self.shape + (5,):
+            raise SgpError(f"state must be {self.torch_dtype} of shape {self.shape + (5,)}, got {psi.dtype} "
                            f"{tuple(psi.shape)}")
         if not psi.is_contiguous() or psi.device != self.device:
             raise SgpError("state must be contiguous on the solver's device")
@@ -131,6 +148,17 @@ class Solver:
         out = (ctypes.c_double * 4)()
         _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
         return np.array(out[:])
+
+    def time_pass(self, psi, pass_kind, reps):
+        """Average milliseconds of one pass (0 X, 1 Y, 2 Z, 3 inverse Y) over reps
+        back-to-back launches, timed with HIP events on the library's stream."""
+        ms = ctypes.c_double()
+        _check(lib().sgp_time_pass(self._ctx, self._psi_ptr(psi), int(pass_kind), int(reps), ctypes.byref(ms)),
+               self._ctx)
+        return ms.value
+
+    def set_graph(self, on):
+        _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)
 
     @property
     def time(self):

@@ -16,9 +16,16 @@ def run_gpu(cfg_or_shape, L, params, psi0, order, tau, nsteps, dtype="complex128
     s = Solver(shape, L, params, dtype=dtype)
     s.build_propagator(tau, order)
     s.time = t0
-    psi = torch.from_numpy(psi0).to(s.torch_dtype).to(s.device).contiguous()
+    psi = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).contiguous()
     for n in (chunks if chunks is not None else [nsteps]):
         s.step(psi, n)
     torch.cuda.synchronize()
-    out = psi.cpu().numpy().astype(np.complex128)
+    out = Solver.from_device_layout(psi.cpu().numpy().astype(np.complex128))
     return out, s
+
+
+def to_gpu(s, psi0):
+    """numpy (5, ...) complex128 -> device tensor in the library layout."""
+    import torch
+    from paper_2603_25282_amd.sgp import Solver
+    return torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).contiguous()
