@@ -34,6 +34,8 @@ def lib():
         L.orc_evolve.argtypes = [ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_long,
                                  ctypes.c_double, ctypes.c_int, dp]
         L.orc_observables.argtypes = [ctypes.c_int, ip, dp, dp, ctypes.c_double, dp, dp]
+        L.orc_adjoint.argtypes = [ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_long,
+                                  ctypes.c_double, dp, dp, dp, dp, ctypes.c_long]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         if "OMP_NUM_THREADS" not in os.environ:
@@ -141,3 +143,17 @@ def observables(psi, L, params, theta=0.0):
     lib().orc_observables(dim, _i(n), _d(Ls), _d(_params(params)), float(theta), _d(a.view(np.float64)),
                           _d(out))
     return out
+
+
+def adjoint(psi0, gT, L, params, order, tau, nsteps, t0=0.0, K=50):
+    """Discrete adjoint of evolve(): given gT = 2 dJ/d conj(Phi(T)) returns
+    (g0 = 2 dJ/d conj(Psi0), dJ/d(gamma, Omega, c0, c1, c2)) for the rotating-frame
+    evolution, with checkpoints every K steps."""
+    a = np.ascontiguousarray(np.array(psi0, dtype=np.complex128))
+    gt = np.ascontiguousarray(np.array(gT, dtype=np.complex128))
+    dim, n, Ls = _grid(a.shape[1:], L)
+    g0 = np.zeros_like(a)
+    dpar = np.zeros(5)
+    lib().orc_adjoint(dim, _i(n), _d(Ls), _d(_params(params)), int(order), float(tau), int(nsteps), float(t0),
+                      _d(a.view(np.float64)), _d(gt.view(np.float64)), _d(g0.view(np.float64)), _d(dpar), int(K))
+    return g0, dpar

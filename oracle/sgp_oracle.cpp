@@ -29,6 +29,44 @@ typedef std::complex<double> cd;
 static const double PI = 3.14159265358979323846264338327950288;
 static const cd I1(0.0, 1.0);
 
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers and a small complex type over them.  The nonlinear
+// flow and the closed-form propagator are written once, templated on the real type,
+// so that the adjoint (below) differentiates exactly the functions the forward
+// evolution uses.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual(double v_ = 0.0, double d_ = 0.0) : v(v_), d(d_) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dual operator/(Dual a, Dual b) { return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+static inline Dual sqrt(Dual a) { double r = std::sqrt(a.v); return Dual(r, r > 0.0 ? a.d / (2.0 * r) : 0.0); }
+static inline Dual sin(Dual a) { return Dual(std::sin(a.v), a.d * std::cos(a.v)); }
+static inline Dual cos(Dual a) { return Dual(std::cos(a.v), -a.d * std::sin(a.v)); }
+static inline double val(double x) { return x; }
+static inline double val(Dual x) { return x.v; }
+
+template <class R>
+struct Cx {
+  R re, im;
+  Cx(R r = R(0.0), R i = R(0.0)) : re(r), im(i) {}
+};
+template <class R> static inline Cx<R> operator+(Cx<R> a, Cx<R> b) { return Cx<R>(a.re + b.re, a.im + b.im); }
+template <class R> static inline Cx<R> operator-(Cx<R> a, Cx<R> b) { return Cx<R>(a.re - b.re, a.im - b.im); }
+template <class R> static inline Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return Cx<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class R> static inline Cx<R> operator*(R s, Cx<R> a) { return Cx<R>(s * a.re, s * a.im); }
+template <class R> static inline Cx<R> cconj(Cx<R> a) { return Cx<R>(a.re, R(0.0) - a.im); }
+template <class R> static inline R cnorm(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+template <class R> static inline Cx<R> expi(R x) { return Cx<R>(cos(x), sin(x)); }
+template <class R> static inline Cx<R> cx_of(cd z) { return Cx<R>(R(z.real()), R(z.imag())); }
+static inline cd to_cd(Cx<double> z) { return cd(z.re, z.im); }
+
 struct OGrid {
   int dim;        // 2 or 3
   int n[3];       // nx, ny, nz (nz = 1 in 2D)
@@ -131,57 +169,67 @@ static inline double wavenumber(int k, int n, double L) {
 // cancellation).  lam = 0 (Omega = 0 and nu_perp = 0) gives the identity.
 // out is row-major 5x5.
 // ---------------------------------------------------------------------------
-static void propagator(double Omega, double gamma, double nu_p, double nu_q,
-                       double tau, cd* out) {
-  cd a(-nu_q, -nu_p);
-  double xi = gamma * std::abs(a);
-  double lam = std::sqrt(Omega * Omega + xi * xi);
-  for (int i = 0; i < 25; ++i) out[i] = 0.0;
-  if (lam == 0.0) {
-    for (int i = 0; i < 5; ++i) out[i * 5 + i] = 1.0;
+template <class R>
+static void propagator_t(R Omega, R gamma, double nu_p, double nu_q, R tau, Cx<R>* out) {
+  const double are = -nu_q, aim = -nu_p;  // a = -nu_q - i nu_p
+  const double amod = std::sqrt(are * are + aim * aim);
+  R xi = gamma * R(amod);
+  R lam = sqrt(Omega * Omega + xi * xi);
+  for (int i = 0; i < 25; ++i) out[i] = Cx<R>();
+  if (val(lam) == 0.0) {
+    for (int i = 0; i < 5; ++i) out[i * 5 + i] = Cx<R>(R(1.0));
     return;
   }
-  double s1 = std::sin(lam * tau), s2 = std::sin(0.5 * lam * tau);
-  cd eta1 = -2.0 * s1 * s1;
-  cd eta2 = -2.0 * s2 * s2;
-  cd eta3 = I1 * std::sin(2.0 * lam * tau);
-  cd eta4 = I1 * s1;
-  double O = Omega, O2 = O * O, O3 = O2 * O, O4 = O2 * O2;
-  double x2 = xi * xi, x4 = x2 * x2;
-  double l2 = lam * lam, l3 = l2 * lam, l4 = l2 * l2;
-  double g = gamma, g2 = g * g, g3 = g2 * g, g4 = g2 * g2;
-  double r6 = std::sqrt(6.0);
+  R s1 = sin(lam * tau), s2 = sin(R(0.5) * lam * tau);
+  Cx<R> eta1(R(-2.0) * s1 * s1);
+  Cx<R> eta2(R(-2.0) * s2 * s2);
+  Cx<R> eta3(R(0.0), sin(R(2.0) * lam * tau));
+  Cx<R> eta4(R(0.0), s1);
+  R O = Omega, O2 = O * O, O3 = O2 * O, O4 = O2 * O2;
+  R x2 = xi * xi, x4 = x2 * x2;
+  R l2 = lam * lam, l3 = l2 * lam, l4 = l2 * l2;
+  R g = gamma, g2 = g * g, g3 = g2 * g, g4 = g2 * g2;
+  R r6 = R(std::sqrt(6.0));
+  const R two(2.0), three(3.0), four(4.0), eight(8.0), one(1.0);
+  Cx<R> L4(l4 * eight);
+  Cx<R> c11 = (one / (eight * l4)) * ((eight * O4 + eight * O2 * x2 + x4) * eta1 + (four * x2 * (two * O2 + x2)) * eta2
+                                      - (four * O * lam * (two * O2 + x2)) * eta3 - (eight * O * lam * x2) * eta4 + L4);
+  Cx<R> c12 = (g / (four * l4)) * ((R(0.0) - O * (four * O2 + three * x2)) * eta1 + (four * O3) * eta2 +
+                                   (lam * (four * O2 + x2)) * eta3 - (two * lam * (two * O2 - x2)) * eta4);
+  Cx<R> c13 = (r6 * g2 / (four * l4)) * (((two * O2 + x2) * eta2 - (two * O * lam) * eta4 + Cx<R>(two * l2)) * eta2);
+  Cx<R> c14 = (g3 / (two * l4)) * (((R(0.0) - O) * eta2 + lam * eta4) * eta2);
+  Cx<R> c15 = (g4 / (eight * l4)) * (eta1 - four * eta2);
+  Cx<R> c22 = (one / (two * l4)) * (((two * x2) * eta2 + Cx<R>(l2)) * ((two * O2 + x2) * eta2 - (two * O * lam) * eta4 +
+                                                                      Cx<R>(two * l2)));
+  Cx<R> c23 = (r6 * g / (two * l4)) * ((x2 * eta2 + Cx<R>(l2)) * ((R(0.0) - O) * eta2 + lam * eta4));
+  Cx<R> c24 = (g2 / (two * l4)) * (((two * x2) * eta2 + Cx<R>(three * l2)) * eta2);
+  Cx<R> c25 = c14 + (O * g3 / l4) * (eta2 * eta2);
+  Cx<R> c33 = (three * x2 / (four * l4)) * (x2 * eta1 + (four * O2) * eta2) + Cx<R>(one);
+  Cx<R> c34 = c23 + (r6 * O * g / l4) * ((x2 * eta2 + Cx<R>(l2)) * eta2);
+  Cx<R> c35 = c13 + (r6 * O * g2 / l3) * (eta2 * eta4);
+  Cx<R> c44 = c22 + (two * O / l3) * (((two * x2) * eta2 + Cx<R>(l2)) * eta4);
+  Cx<R> c45 = c12 + (O * g / (two * l4)) * (((four * O2 + three * x2)) * eta1 - (four * O2) * eta2);
+  Cx<R> c55 = c11 + (O / l3) * ((two * O2 + x2) * eta3 + (two * x2) * eta4);
 
-  cd c11 = (1.0 / (8.0 * l4)) * ((8.0 * O4 + 8.0 * O2 * x2 + x4) * eta1 + 4.0 * x2 * (2.0 * O2 + x2) * eta2
-                                 - 4.0 * O * lam * (2.0 * O2 + x2) * eta3 - 8.0 * O * lam * x2 * eta4 + 8.0 * l4);
-  cd c12 = (g / (4.0 * l4)) * (-O * (4.0 * O2 + 3.0 * x2) * eta1 + 4.0 * O3 * eta2 + lam * (4.0 * O2 + x2) * eta3
-                               - 2.0 * lam * (2.0 * O2 - x2) * eta4);
-  cd c13 = (r6 * g2 / (4.0 * l4)) * ((2.0 * O2 + x2) * eta2 - 2.0 * O * lam * eta4 + 2.0 * l2) * eta2;
-  cd c14 = (g3 / (2.0 * l4)) * (-O * eta2 + lam * eta4) * eta2;
-  cd c15 = (g4 / (8.0 * l4)) * (eta1 - 4.0 * eta2);
-  cd c22 = (1.0 / (2.0 * l4)) * (2.0 * x2 * eta2 + l2) * ((2.0 * O2 + x2) * eta2 - 2.0 * O * lam * eta4 + 2.0 * l2);
-  cd c23 = (r6 * g / (2.0 * l4)) * (x2 * eta2 + l2) * (-O * eta2 + lam * eta4);
-  cd c24 = (g2 / (2.0 * l4)) * (2.0 * x2 * eta2 + 3.0 * l2) * eta2;
-  cd c25 = c14 + (O * g3 / l4) * eta2 * eta2;
-  cd c33 = (3.0 * x2 / (4.0 * l4)) * (x2 * eta1 + 4.0 * O2 * eta2) + 1.0;
-  cd c34 = c23 + (r6 * O * g / l4) * (x2 * eta2 + l2) * eta2;
-  cd c35 = c13 + (r6 * O * g2 / l3) * eta2 * eta4;
-  cd c44 = c22 + (2.0 * O / l3) * (2.0 * x2 * eta2 + l2) * eta4;
-  cd c45 = c12 + (O * g / (2.0 * l4)) * ((4.0 * O2 + 3.0 * x2) * eta1 - 4.0 * O2 * eta2);
-  cd c55 = c11 + (O / l3) * ((2.0 * O2 + x2) * eta3 + 2.0 * x2 * eta4);
-
-  cd c[5][5];
+  Cx<R> c[5][5];
   c[0][0] = c11; c[0][1] = c12; c[0][2] = c13; c[0][3] = c14; c[0][4] = c15;
   c[1][1] = c22; c[1][2] = c23; c[1][3] = c24; c[1][4] = c25;
   c[2][2] = c33; c[2][3] = c34; c[2][4] = c35;
   c[3][3] = c44; c[3][4] = c45;
   c[4][4] = c55;
-  cd apow[5], abpow[5];
-  apow[0] = abpow[0] = 1.0;
-  for (int k = 1; k < 5; ++k) { apow[k] = apow[k - 1] * a; abpow[k] = abpow[k - 1] * std::conj(a); }
+  Cx<R> a{R(are), R(aim)}, ab{R(are), R(-aim)};
+  Cx<R> apow[5], abpow[5];
+  apow[0] = abpow[0] = Cx<R>(R(1.0));
+  for (int k = 1; k < 5; ++k) { apow[k] = apow[k - 1] * a; abpow[k] = abpow[k - 1] * ab; }
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j < 5; ++j)
       out[i * 5 + j] = (j >= i) ? apow[j - i] * c[i][j] : abpow[i - j] * c[j][i];
+}
+
+static void propagator(double Omega, double gamma, double nu_p, double nu_q, double tau, cd* out) {
+  Cx<double> o[25];
+  propagator_t<double>(Omega, gamma, nu_p, nu_q, tau, o);
+  for (int i = 0; i < 25; ++i) out[i] = to_cd(o[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -227,87 +275,115 @@ static void linear_step(const OGrid& g, const OParams& P, double delta, cd* psi)
 // Limits the paper leaves implicit: S = 0 uses sin(c2 S d)/S = c2 d; |F| = 0 makes
 // the spin rotation the identity; S^2 < 0 from rounding is clamped to 0.
 // ---------------------------------------------------------------------------
-static void ff_matrix(double Fx, double Fy, double Fz, cd* M) {
+template <class R>
+static void ff_matrix(R Fx, R Fy, R Fz, Cx<R>* M) {
   // F.f (Sec. 1): diagonal F_z (2,1,0,-1,-2); F_- above, F_+ below with the
   // sqrt6/2 weights on the middle links.
-  cd Fp(Fx, Fy), Fm(Fx, -Fy);
-  double h6 = std::sqrt(6.0) / 2.0;
-  for (int i = 0; i < 25; ++i) M[i] = 0.0;
-  M[0 * 5 + 0] = 2.0 * Fz; M[1 * 5 + 1] = Fz; M[2 * 5 + 2] = 0.0; M[3 * 5 + 3] = -Fz; M[4 * 5 + 4] = -2.0 * Fz;
+  Cx<R> Fp(Fx, Fy), Fm(Fx, R(0.0) - Fy);
+  R h6 = R(std::sqrt(6.0) / 2.0);
+  for (int i = 0; i < 25; ++i) M[i] = Cx<R>();
+  M[0 * 5 + 0] = Cx<R>(R(2.0) * Fz); M[1 * 5 + 1] = Cx<R>(Fz); M[3 * 5 + 3] = Cx<R>(R(0.0) - Fz);
+  M[4 * 5 + 4] = Cx<R>(R(-2.0) * Fz);
   M[0 * 5 + 1] = Fm;      M[1 * 5 + 0] = Fp;
   M[1 * 5 + 2] = h6 * Fm; M[2 * 5 + 1] = h6 * Fp;
   M[2 * 5 + 3] = h6 * Fm; M[3 * 5 + 2] = h6 * Fp;
   M[3 * 5 + 4] = Fm;      M[4 * 5 + 3] = Fp;
 }
 
-static void matmul5(const cd* A, const cd* B, cd* C) {
+template <class R>
+static void matmul5(const Cx<R>* A, const Cx<R>* B, Cx<R>* C) {
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j < 5; ++j) {
-      cd acc = 0.0;
-      for (int k = 0; k < 5; ++k) acc += A[i * 5 + k] * B[k * 5 + j];
+      Cx<R> acc;
+      for (int k = 0; k < 5; ++k) acc = acc + A[i * 5 + k] * B[k * 5 + j];
       C[i * 5 + j] = acc;
     }
 }
 
-struct Densities { double rho, Fx, Fy, Fz; cd A00; };
+template <class R>
+struct DensitiesT { R rho, Fx, Fy, Fz; Cx<R> A00; };
 
-static Densities densities(const cd* psi) {
+template <class R>
+static DensitiesT<R> densities_t(const Cx<R>* psi) {
   // Sec. 1: rho = sum |psi_l|^2, F_x, F_y, F_z, A00 = (2 psi2 psi-2 - 2 psi1 psi-1 + psi0^2)/sqrt5.
-  const cd &p2 = psi[0], &p1 = psi[1], &p0 = psi[2], &m1 = psi[3], &m2 = psi[4];
-  double h6 = std::sqrt(6.0) / 2.0;
-  Densities d;
-  d.rho = std::norm(p2) + std::norm(p1) + std::norm(p0) + std::norm(m1) + std::norm(m2);
-  cd fx = std::conj(p1) * p2 + std::conj(p2) * p1 + std::conj(m2) * m1 + std::conj(m1) * m2
-          + h6 * (std::conj(p0) * p1 + std::conj(p1) * p0 + std::conj(m1) * p0 + std::conj(p0) * m1);
-  cd fy = I1 * (std::conj(p1) * p2 - std::conj(p2) * p1 + std::conj(m2) * m1 - std::conj(m1) * m2
-                + h6 * (std::conj(p0) * p1 - std::conj(p1) * p0 + std::conj(m1) * p0 - std::conj(p0) * m1));
-  d.Fx = fx.real();
-  d.Fy = fy.real();
-  d.Fz = 2.0 * std::norm(p2) + std::norm(p1) - std::norm(m1) - 2.0 * std::norm(m2);
-  d.A00 = (2.0 * p2 * m2 - 2.0 * p1 * m1 + p0 * p0) / std::sqrt(5.0);
+  const Cx<R> &p2 = psi[0], &p1 = psi[1], &p0 = psi[2], &m1 = psi[3], &m2 = psi[4];
+  const R h6 = R(std::sqrt(6.0) / 2.0), two(2.0);
+  DensitiesT<R> d;
+  d.rho = cnorm(p2) + cnorm(p1) + cnorm(p0) + cnorm(m1) + cnorm(m2);
+  Cx<R> fx = cconj(p1) * p2 + cconj(p2) * p1 + cconj(m2) * m1 + cconj(m1) * m2
+             + h6 * (cconj(p0) * p1 + cconj(p1) * p0 + cconj(m1) * p0 + cconj(p0) * m1);
+  Cx<R> fy = Cx<R>(R(0.0), R(1.0)) * (cconj(p1) * p2 - cconj(p2) * p1 + cconj(m2) * m1 - cconj(m1) * m2
+                                      + h6 * (cconj(p0) * p1 - cconj(p1) * p0 + cconj(m1) * p0 - cconj(p0) * m1));
+  d.Fx = fx.re;
+  d.Fy = fy.re;
+  d.Fz = two * cnorm(p2) + cnorm(p1) - cnorm(m1) - two * cnorm(m2);
+  d.A00 = R(1.0 / std::sqrt(5.0)) * (two * (p2 * m2) - two * (p1 * m1) + p0 * p0);
   return d;
 }
 
-static void nl_point(const OParams& P, double V, double delta, cd* psi) {
-  Densities d = densities(psi);
-  double S2 = (d.rho / 5.0) * (d.rho / 5.0) - std::norm(d.A00) / 5.0;
-  if (S2 < 0.0) S2 = 0.0;
-  double S = std::sqrt(S2);
-  double cs = std::cos(P.c2 * S * delta);
-  double sn_over_S = (S == 0.0) ? P.c2 * delta : std::sin(P.c2 * S * delta) / S;
+// Exact nonlinear flow at one point for time delta (Sec. 3.2, eq. solution2), with
+// the interaction constants and the trap value as (possibly dual) reals.
+template <class R>
+static void nl_point_t(R c0, R c1, R c2, R V, R delta, Cx<R>* psi) {
+  DensitiesT<R> d = densities_t(psi);
+  const R five(5.0);
+  R S2 = (d.rho / five) * (d.rho / five) - cnorm(d.A00) / five;
+  if (val(S2) < 0.0) S2 = R(0.0);
+  R S = sqrt(S2);
+  R cs = cos(c2 * S * delta);
+  R sn_over_S = (val(S) == 0.0) ? c2 * delta : sin(c2 * S * delta) / S;
   // (A conj Psi)_i = (-1)^(i-1) conj(psi_{6-i}) / sqrt5 with 1-based i (Sec. 1).
-  double r5 = 1.0 / std::sqrt(5.0);
-  cd Apsib[5] = { r5 * std::conj(psi[4]), -r5 * std::conj(psi[3]), r5 * std::conj(psi[2]),
-                  -r5 * std::conj(psi[1]), r5 * std::conj(psi[0]) };
-  cd b[5];
+  const R r5(1.0 / std::sqrt(5.0));
+  Cx<R> Apsib[5] = {r5 * cconj(psi[4]), (R(0.0) - r5) * cconj(psi[3]), r5 * cconj(psi[2]),
+                    (R(0.0) - r5) * cconj(psi[1]), r5 * cconj(psi[0])};
+  const Cx<R> I(R(0.0), R(1.0));
+  Cx<R> b[5];
   for (int i = 0; i < 5; ++i)
-    b[i] = cs * psi[i] + I1 * sn_over_S * ((d.rho / 5.0) * psi[i] - d.A00 * Apsib[i]);
+    b[i] = cs * psi[i] + sn_over_S * (I * ((d.rho / five) * psi[i] - d.A00 * Apsib[i]));
 
   // exp(-i c1 d F.f) = I + i g1 N + g2 N^2 + i g3 N^3 + g4 N^4, N = F.f/|F|.
-  double Fabs = std::sqrt(d.Fx * d.Fx + d.Fy * d.Fy + d.Fz * d.Fz);
-  cd R[25];
-  for (int i = 0; i < 25; ++i) R[i] = 0.0;
-  for (int i = 0; i < 5; ++i) R[i * 5 + i] = 1.0;
-  if (Fabs > 0.0) {
-    double kap = P.c1 * Fabs * delta;
-    double g1 = std::sin(2.0 * kap) / 6.0 - 4.0 / 3.0 * std::sin(kap);
-    double g2 = 4.0 / 3.0 * std::cos(kap) - std::cos(2.0 * kap) / 12.0 - 5.0 / 4.0;
-    double g3 = std::sin(kap) / 3.0 - std::sin(2.0 * kap) / 6.0;
-    double g4 = std::cos(2.0 * kap) / 12.0 - std::cos(kap) / 3.0 + 0.25;
-    cd N1[25], N2[25], N3[25], N4[25];
+  R Fabs = sqrt(d.Fx * d.Fx + d.Fy * d.Fy + d.Fz * d.Fz);
+  Cx<R> Rm[25];
+  for (int i = 0; i < 25; ++i) Rm[i] = Cx<R>();
+  for (int i = 0; i < 5; ++i) Rm[i * 5 + i] = Cx<R>(R(1.0));
+  if (val(Fabs) > 0.0) {
+    R kap = c1 * Fabs * delta;
+    R g1 = sin(R(2.0) * kap) / R(6.0) - R(4.0 / 3.0) * sin(kap);
+    R g2 = R(4.0 / 3.0) * cos(kap) - cos(R(2.0) * kap) / R(12.0) - R(5.0 / 4.0);
+    R g3 = sin(kap) / R(3.0) - sin(R(2.0) * kap) / R(6.0);
+    R g4 = cos(R(2.0) * kap) / R(12.0) - cos(kap) / R(3.0) + R(0.25);
+    Cx<R> N1[25], N2[25], N3[25], N4[25];
     ff_matrix(d.Fx / Fabs, d.Fy / Fabs, d.Fz / Fabs, N1);
     matmul5(N1, N1, N2);
     matmul5(N2, N1, N3);
     matmul5(N3, N1, N4);
     for (int i = 0; i < 25; ++i)
-      R[i] += I1 * g1 * N1[i] + g2 * N2[i] + I1 * g3 * N3[i] + g4 * N4[i];
+      Rm[i] = Rm[i] + I * (g1 * N1[i]) + g2 * N2[i] + I * (g3 * N3[i]) + g4 * N4[i];
   }
-  cd ph = std::exp(cd(0.0, -delta * (V + (P.c0 + P.c2 / 5.0) * d.rho)));
+  Cx<R> ph = expi(R(0.0) - delta * (V + (c0 + c2 / five) * d.rho));
   for (int i = 0; i < 5; ++i) {
-    cd acc = 0.0;
-    for (int j = 0; j < 5; ++j) acc += R[i * 5 + j] * b[j];
+    Cx<R> acc;
+    for (int j = 0; j < 5; ++j) acc = acc + Rm[i * 5 + j] * b[j];
     psi[i] = ph * acc;
   }
+}
+
+static void nl_point(const OParams& P, double V, double delta, cd* psi) {
+  Cx<double> v[5];
+  for (int i = 0; i < 5; ++i) v[i] = cx_of<double>(psi[i]);
+  nl_point_t<double>(P.c0, P.c1, P.c2, V, delta, v);
+  for (int i = 0; i < 5; ++i) psi[i] = to_cd(v[i]);
+}
+
+struct Densities { double rho, Fx, Fy, Fz; cd A00; };
+
+static Densities densities(const cd* psi) {
+  Cx<double> v[5];
+  for (int i = 0; i < 5; ++i) v[i] = cx_of<double>(psi[i]);
+  DensitiesT<double> t = densities_t(v);
+  Densities d;
+  d.rho = t.rho; d.Fx = t.Fx; d.Fy = t.Fy; d.Fz = t.Fz; d.A00 = to_cd(t.A00);
+  return d;
 }
 
 // Trap of eq. (harmonic) evaluated at the rotated point R(theta) x, with
@@ -433,6 +509,150 @@ static void evolve(const OGrid& g, const OParams& P, int order, double tau, long
     }
     t = t0 + (double)(n + 1) * tau;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the evolution (gradient of a real loss J(Phi(T))).
+// Convention: g = 2 dJ/d conj(Phi), i.e. dJ = Re sum_x conj(g) dPhi.
+//  * linear substep L(d): L is unitary for this pairing and L(d)^H = L(-d);
+//  * nonlinear substep: the real-linear Jacobian of nl_point_t at the stored input,
+//    column by column with dual numbers (10 real directions per point);
+//  * parameter partials with one more dual direction each: gamma and Omega through
+//    the closed-form propagator, c0, c1, c2 through the nonlinear flow, Omega also
+//    through the rotated trap (dV/dOmega = s (gx^2 - gy^2) X Y).
+// Checkpoints every K steps; each segment is recomputed storing substep inputs.
+// dpar = (gamma, Omega, c0, c1, c2).
+// ---------------------------------------------------------------------------
+static void nl_adjoint_step(const OGrid& g, const OParams& P, double delta, double s, const cd* psi_in,
+                            cd* gvec, double* dpar) {
+  long np = npoints(g);
+  int nx = g.n[0], ny = g.n[1];
+  const double theta = P.Omega * s;
+  double acc[4] = {0, 0, 0, 0};  // Omega, c0, c1, c2
+#pragma omp parallel
+  {
+    double loc[4] = {0, 0, 0, 0};
+#pragma omp for schedule(static)
+    for (long idx = 0; idx < np; ++idx) {
+      int ix = (int)(idx % nx), iy = (int)((idx / nx) % ny), iz = (int)(idx / ((long)nx * ny));
+      double x = coord(g, 0, ix), y = coord(g, 1, iy), z = (g.dim == 3) ? coord(g, 2, iz) : 0.0;
+      double V = trap_rotated(P, theta, x, y, z);
+      double c = std::cos(theta), sn = std::sin(theta);
+      double X = c * x + sn * y, Y = -sn * x + c * y;
+      double dVdO = s * (P.gx * P.gx - P.gy * P.gy) * X * Y;
+      cd pin[5], gout[5], gin[5];
+      for (int i = 0; i < 5; ++i) { pin[i] = psi_in[i * np + idx]; gout[i] = gvec[i * np + idx]; }
+      auto run = [&](const cd* tangent, Dual c0, Dual c1, Dual c2, Dual Vd) {
+        Cx<Dual> v[5];
+        for (int k = 0; k < 5; ++k)
+          v[k] = Cx<Dual>(Dual(pin[k].real(), tangent[k].real()), Dual(pin[k].imag(), tangent[k].imag()));
+        nl_point_t<Dual>(c0, c1, c2, Vd, Dual(delta), v);
+        double r = 0.0;
+        for (int k = 0; k < 5; ++k) r += gout[k].real() * v[k].re.d + gout[k].imag() * v[k].im.d;
+        return r;  // Re <gout, D tangent>
+      };
+      const cd zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < 5; ++j) {
+        cd t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        t[j] = 1.0;
+        double re = run(t, Dual(P.c0), Dual(P.c1), Dual(P.c2), Dual(V));
+        t[j] = I1;
+        double im = run(t, Dual(P.c0), Dual(P.c1), Dual(P.c2), Dual(V));
+        gin[j] = cd(re, im);
+      }
+      loc[0] += run(zero, Dual(P.c0), Dual(P.c1), Dual(P.c2), Dual(V, dVdO));
+      loc[1] += run(zero, Dual(P.c0, 1.0), Dual(P.c1), Dual(P.c2), Dual(V));
+      loc[2] += run(zero, Dual(P.c0), Dual(P.c1, 1.0), Dual(P.c2), Dual(V));
+      loc[3] += run(zero, Dual(P.c0), Dual(P.c1), Dual(P.c2, 1.0), Dual(V));
+      for (int i = 0; i < 5; ++i) gvec[i * np + idx] = gin[i];
+    }
+#pragma omp critical
+    for (int q = 0; q < 4; ++q) acc[q] += loc[q];
+  }
+  dpar[1] += acc[0];
+  dpar[2] += acc[1];
+  dpar[3] += acc[2];
+  dpar[4] += acc[3];
+}
+
+// Partials of Re <gout, L(d) phi_in> with respect to gamma and Omega.
+static void linear_param_partials(const OGrid& g, const OParams& P, double delta, const cd* phi_in, const cd* gout,
+                                  double* dpar) {
+  long np = npoints(g);
+  int nx = g.n[0], ny = g.n[1], nz = (g.dim == 3 ? g.n[2] : 1);
+  std::vector<cd> hat(phi_in, phi_in + 5 * np), d(5 * np);
+  for (int c = 0; c < 5; ++c) fft_nd(g, hat.data() + c * np, -1);
+  for (int which = 0; which < 2; ++which) {
+#pragma omp parallel for schedule(static)
+    for (long pq = 0; pq < (long)nx * ny; ++pq) {
+      int kx = (int)(pq % nx), ky = (int)(pq / nx);
+      double nup = wavenumber(kx, nx, g.L[0]), nuq = wavenumber(ky, ny, g.L[1]);
+      Cx<Dual> E[25];
+      propagator_t<Dual>(Dual(P.Omega, which == 1 ? 1.0 : 0.0), Dual(P.gamma, which == 0 ? 1.0 : 0.0), nup, nuq,
+                         Dual(delta), E);
+      for (int kz = 0; kz < nz; ++kz) {
+        double nur = (g.dim == 3) ? wavenumber(kz, nz, g.L[2]) : 0.0;
+        cd kin = std::exp(cd(0.0, -0.5 * delta * (nup * nup + nuq * nuq + nur * nur)));
+        long idx = (long)kz * nx * ny + pq;
+        for (int i = 0; i < 5; ++i) {
+          cd acc = 0.0;
+          for (int j = 0; j < 5; ++j) acc += cd(E[i * 5 + j].re.d, E[i * 5 + j].im.d) * hat[j * np + idx];
+          d[i * np + idx] = kin * acc;
+        }
+      }
+    }
+    for (int c = 0; c < 5; ++c) fft_nd(g, d.data() + c * np, +1);
+    double r = 0.0;
+    for (long i = 0; i < 5 * np; ++i) r += (std::conj(gout[i]) * d[i]).real();
+    dpar[which] += r;
+  }
+}
+
+static void adjoint(const OGrid& g, const OParams& P, int order, double tau, long nsteps, double t0,
+                    const cd* psi0, const cd* gT, cd* g0, double* dpar, long K) {
+  long np = npoints(g);
+  Scheme sc = make_scheme(order);
+  for (int q = 0; q < 5; ++q) dpar[q] = 0.0;
+  if (K < 1) K = 1;
+  // forward: checkpoints at the start of every segment
+  std::vector<std::vector<cd>> ckpt;
+  std::vector<cd> psi(psi0, psi0 + 5 * np);
+  for (long n0 = 0; n0 < nsteps; n0 += K) {
+    ckpt.push_back(psi);
+    long ns = std::min(K, nsteps - n0);
+    evolve(g, P, order, tau, ns, t0 + (double)n0 * tau, 0, psi.data());
+  }
+  std::vector<cd> gv(gT, gT + 5 * np);
+  struct Sub { bool nl; double d, s; std::vector<cd> in; };
+  for (long seg = (long)ckpt.size() - 1; seg >= 0; --seg) {
+    long n0 = seg * K, ns = std::min(K, nsteps - n0);
+    std::vector<Sub> subs;
+    std::vector<cd> u = ckpt[seg];
+    for (long n = 0; n < ns; ++n) {
+      double s = t0 + (double)(n0 + n) * tau;
+      for (int j = 0; j < sc.m; ++j) {
+        if (sc.a[j] != 0.0) {
+          subs.push_back({true, sc.a[j] * tau, s, u});
+          nl_step(g, P, sc.a[j] * tau, P.Omega * s, u.data());
+        }
+        if (sc.b[j] != 0.0) {
+          subs.push_back({false, sc.b[j] * tau, s, u});
+          linear_step(g, P, sc.b[j] * tau, u.data());
+          s += sc.b[j] * tau;
+        }
+      }
+    }
+    for (long k = (long)subs.size() - 1; k >= 0; --k) {
+      const Sub& sb = subs[k];
+      if (sb.nl) {
+        nl_adjoint_step(g, P, sb.d, sb.s, sb.in.data(), gv.data(), dpar);
+      } else {
+        linear_param_partials(g, P, sb.d, sb.in.data(), gv.data(), dpar);
+        linear_step(g, P, -sb.d, gv.data());
+      }
+    }
+  }
+  std::copy(gv.begin(), gv.end(), g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +791,14 @@ void orc_rotation_map(int dim, const int* n, const double* L, const double* para
 void orc_evolve(int dim, const int* n, const double* L, const double* params, int order, double tau, long nsteps,
                 double t0, int mode, double* psi) {
   evolve(mkgrid(dim, n, L), mkparams(params), order, tau, nsteps, t0, mode, reinterpret_cast<cd*>(psi));
+}
+
+// Adjoint: gT = 2 dJ/d conj(Phi(T)) -> g0 = 2 dJ/d conj(Psi0) and
+// dpar = dJ/d(gamma, Omega, c0, c1, c2); checkpoints every K steps.
+void orc_adjoint(int dim, const int* n, const double* L, const double* params, int order, double tau, long nsteps,
+                 double t0, const double* psi0, const double* gT, double* g0, double* dpar, long K) {
+  adjoint(mkgrid(dim, n, L), mkparams(params), order, tau, nsteps, t0, reinterpret_cast<const cd*>(psi0),
+          reinterpret_cast<const cd*>(gT), reinterpret_cast<cd*>(g0), dpar, K);
 }
 
 void orc_observables(int dim, const int* n, const double* L, const double* params, double theta, const double* psi,

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function include/sgp.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2603_25282_amd import sgp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sgp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sgp_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", sgp.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(line.split()[-1] for line in out.stdout.splitlines() if line.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = sgp.lib()
+    for n in names:
+        assert hasattr(L, n)
+    assert set(sgp.exported_symbols()) <= set(names)
+
+
+def _create(dim=2, n=(64, 64, 1), L=(8.0, 8.0, 1.0), params=(1, 1, 1, 0.5, 0.5, 1, 1, 1), dtype=0):
+    g = sgp._Grid()
+    g.dim = dim
+    for i in range(3):
+        g.n[i] = n[i]
+        g.L[i] = L[i]
+    p = sgp._Params(*[float(x) for x in params])
+    ctx = ctypes.c_void_p()
+    rc = sgp.lib().sgp_create(ctypes.byref(g), ctypes.byref(p), dtype, None, ctypes.byref(ctx))
+    return rc, ctx
+
+
+def test_create_validates_arguments():
+    L = sgp.lib()
+    for kw in (dict(n=(48, 64, 1)), dict(n=(64, 1024, 1)), dict(L=(0.0, 8.0, 1.0)), dict(dim=4),
+               dict(params=(1, 1, float("nan"), 0, 0, 1, 1, 1)), dict(dtype=7)):
+        rc, ctx = _create(**kw)
+        assert rc == -1, kw
+        assert L.sgp_last_error(None)
+    rc, ctx = _create()
+    assert rc == 0
+    nb = ctypes.c_size_t()
+    assert L.sgp_workspace_size(ctx, ctypes.byref(nb)) == 0 and nb.value > 64 * 64 * 8
+    # calls out of order fail cleanly without a device
+    assert L.sgp_build_propagator(ctx, 1e-3, 2) == -2
+    assert L.sgp_step(ctx, ctypes.c_void_p(1), 1) == -2
+    assert b"workspace" in L.sgp_last_error(ctx)
+    assert L.sgp_set_workspace(ctx, ctypes.c_void_p(256), 1) == -5
+    assert L.sgp_set_option(ctx, 99, 0) == -1
+    t = ctypes.c_double(-1.0)
+    assert L.sgp_set_time(ctx, 0.25) == 0 and L.sgp_get_time(ctx, ctypes.byref(t)) == 0 and t.value == 0.25
+    L.sgp_destroy(ctx)
+
+
+def test_workspace_size_scales_with_grid_and_dtype():
+    L = sgp.lib()
+    sizes = {}
+    for n, dt in ((64, 0), (64, 1), (256, 0)):
+        rc, ctx = _create(n=(n, n, 1), dtype=dt)
+        nb = ctypes.c_size_t()
+        L.sgp_workspace_size(ctx, ctypes.byref(nb))
+        sizes[(n, dt)] = nb.value
+        L.sgp_destroy(ctx)
+    assert sizes[(64, 1)] > sizes[(64, 0)] and sizes[(256, 0)] > 10 * sizes[(64, 0)]

@@ -132,3 +132,33 @@ def test_config2_full_1000_steps(dtype):
     assert err <= TOL[dtype]
     # discrete mass is conserved up to rounding on both sides (6000 substeps)
     assert abs(obs[0] - ref["obs"][0]) <= (1e-11 if dtype == "complex128" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_3d_small_grids(dtype, order):
+    # 3D passes (X, Y forward, Z with the propagator, Y inverse) on C3 physics at
+    # reduced sizes, including an anisotropic in-plane trap so the rotation matters.
+    base = I.with_(I.C3, shape=(16, 32, 64), name="c3-small")
+    p = list(base.params)
+    p[6] = 1.3  # gy
+    cfg = I.with_(base, params=tuple(p))
+    err = case(cfg, dtype, steps=6, order=order)
+    print("rel l2", err)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_3d_observables(dtype):
+    from paper_2603_25282_amd.sgp import Solver
+    from tests.gpu_util import to_gpu
+    cfg = I.with_(I.C3, shape=(32, 32, 64), name="c3-obs")
+    psi0 = I.initial_state(cfg)
+    s = Solver(cfg.shape, cfg.L, cfg.params, dtype=dtype)
+    s.time = 0.2
+    got = s.observables(to_gpu(s, psi0))
+    ref = oracle.observables(psi0, cfg.L, cfg.params, theta=cfg.params[3] * 0.2)
+    print("gpu", got, "oracle", ref)
+    tol = 1e-12 if dtype == "complex128" else 2e-6
+    scale = np.array([1.0, abs(ref[1]) + 1.0, 1.0, 1.0])
+    assert np.all(np.abs(got - ref) <= tol * scale)
