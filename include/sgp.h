@@ -111,6 +111,35 @@ int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
  * FP64 accumulation.  Synchronous. */
 int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
 
+/* ---- Differentiation (discrete adjoint of sgp_step) -------------------------
+ * Convention: for a real loss J of the state, a gradient is g = 2 dJ/d conj(psi),
+ * i.e. dJ = Re sum conj(g) dpsi over all stored values (the convention of
+ * torch.autograd for complex tensors).  The adjoint of the exact linear substep is
+ * the same propagator with -d (P(d)^H = P(-d)); the adjoint of the exact nonlinear
+ * substep (Sec. 3.2, eq. solution2) is its real-linear (Wirtinger) transpose at the
+ * stored forward input.
+ *
+ * Bytes of the store one sgp_step_store(nsteps) call needs: (2M + 1) states, M the
+ * number of linear substeps (TS2: nsteps, TS4: 3 nsteps). */
+int sgp_store_size(const sgp_ctx* ctx, long nsteps, size_t* bytes);
+
+/* sgp_step() that also writes, for every pass, the input of its pointwise stage
+ * into the caller-owned device buffer `store` (slot 2k: the k-th nonlinear
+ * substep's input in physical space; slot 2k+1: the k-th propagator's input in
+ * Fourier space).  No graph replay.  Advances the clock like sgp_step(). */
+int sgp_step_store(sgp_ctx* ctx, void* psi_dev, long nsteps, void* store, size_t store_bytes);
+
+/* Reverse sweep of the sgp_step_store(nsteps) call that started at the current
+ * clock (set it back with sgp_set_time first).  lam_dev: on entry the gradient with
+ * respect to that call's output, on exit with respect to its input (same layout as
+ * the state).  Parameter gradients are accumulated on the device (FP64, one slot per
+ * block, deterministic order).  Asynchronous; does not move the clock. */
+int sgp_adjoint_segment(sgp_ctx* ctx, void* lam_dev, long nsteps, const void* store, size_t store_bytes);
+
+/* Accumulated dJ/d(gamma, Omega, c0, c1, c2) of all sgp_adjoint_segment() calls since
+ * the last reset; reset = 1 clears the accumulators.  Synchronous. */
+int sgp_adjoint_gradients(sgp_ctx* ctx, double out[5], int reset);
+
 /* Rotation clock t (the time of the rotating frame the state lives in). */
 int sgp_get_time(const sgp_ctx* ctx, double* t);
 int sgp_set_time(sgp_ctx* ctx, double t);

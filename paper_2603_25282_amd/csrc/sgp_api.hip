@@ -77,6 +77,8 @@ struct sgp_ctx {
   size_t off_kin[2][3];
   size_t off_clock;
   size_t off_part;
+  size_t off_gacc;
+  long ngacc = 0;  // blocks with a gradient slot
 
   int scheme = 0;
   double tau = 0.0;
@@ -220,6 +222,39 @@ hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi
   a.d = d;
   a.advance_clock = (mode == C_PROP) ? 1 : 0;
   return launch_pass<T>(mode, psi, a, c->g.n[axis], st);
+}
+
+// Store-mode and adjoint variants of the passes.
+template <typename T>
+hipError_t run_xpass_ex(sgp_ctx* c, int kind, void* psi, double d, int clock_mode, double s_arg, void* store,
+                        const void* fwd) {
+  PassArgs a = base_args(c);
+  a.tw_fwd = c->at(c->off_tw[0][0]);
+  a.tw_inv = c->at(c->off_tw[0][1]);
+  a.d = d;
+  a.s_arg = s_arg;
+  a.clock_mode = clock_mode;
+  a.store = store;
+  a.fwd = fwd;
+  a.gacc = (double*)c->at(c->off_gacc);
+  return launch_pass<T>(kind, psi, a, c->g.n[0], c->st);
+}
+
+template <typename T>
+hipError_t run_colpass_ex(sgp_ctx* c, int kind, int axis, void* psi, int table, double d, void* store,
+                          const void* fwd) {
+  PassArgs a = base_args(c);
+  column_geometry(c, axis, a);
+  a.cs = c->at(c->off_cs[table]);
+  a.kin_a = c->at(c->off_kin[table][0]);
+  a.kin_o = c->at(c->off_kin[table][1]);
+  a.kin_l = c->at(c->off_kin[table][axis]);
+  a.d = d;
+  a.advance_clock = (kind == C_PROP) ? 1 : 0;
+  a.store = store;
+  a.fwd = fwd;
+  a.gacc = (double*)c->at(c->off_gacc);
+  return launch_pass<T>(kind, psi, a, c->g.n[axis], c->st);
 }
 
 // One exact linear substep on x-transformed data: 2D Y-pass, 3D Y1 + Z + Y2.
@@ -423,6 +458,70 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
   return SGP_OK;
 }
 
+// Forward evolution of one call that also stores, for every pass with a pointwise
+// stage, the stage's input: slot 2k the input of the k-th nonlinear substep
+// (physical), slot 2k+1 the Fourier-space input of the k-th propagator.  Kernels are
+// launched one by one (each pass writes a different slot).
+template <typename T>
+int step_store_impl(sgp_ctx* c, void* psi, long nsteps, char* store) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(c, nsteps, nl, lin, tab);
+  const size_t slot = (size_t)c->npts() * 5 * 2 * c->esize;
+  hipError_t e = run_xpass_ex<T>(c, X_FIRST, psi, nl[0], CLOCK_ARG, c->t, store, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
+  double s = c->t;
+  for (size_t k = 0; k < lin.size(); ++k) {
+    char* sl = store + (2 * k + 1) * slot;
+    if (c->g.dim == 2) {
+      e = run_colpass_ex<T>(c, C_PROP, 1, psi, tab[k], lin[k], sl, nullptr);
+    } else {
+      e = run_colpass_ex<T>(c, C_FWD, 1, psi, tab[k], lin[k], nullptr, nullptr);
+      if (e == hipSuccess) e = run_colpass_ex<T>(c, C_PROP, 2, psi, tab[k], lin[k], sl, nullptr);
+      if (e == hipSuccess) e = run_colpass_ex<T>(c, C_INV, 1, psi, tab[k], lin[k], nullptr, nullptr);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "linear pass launch");
+    s += lin[k];
+    e = run_xpass_ex<T>(c, k + 1 == lin.size() ? X_LAST : X_MID, psi, nl[k + 1], CLOCK_ARG, s,
+                        store + (2 * k + 2) * slot, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
+  }
+  c->t += (double)nsteps * c->tau;
+  return SGP_OK;
+}
+
+// Reverse sweep through the passes of the matching step_store_impl call (started at
+// the current clock).  lam: gradient with respect to the call's output on entry, with
+// respect to its input on exit (physical space both times).
+template <typename T>
+int adjoint_impl(sgp_ctx* c, void* lam, long nsteps, const char* store) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(c, nsteps, nl, lin, tab);
+  const size_t slot = (size_t)c->npts() * 5 * 2 * c->esize;
+  const size_t M = lin.size();
+  std::vector<double> s(M + 1);
+  s[0] = c->t;
+  for (size_t k = 0; k < M; ++k) s[k + 1] = s[k] + lin[k];
+  hipError_t e = run_xpass_ex<T>(c, XA_LAST, lam, nl[M], CLOCK_ARG, s[M], nullptr, store + 2 * M * slot);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint X-pass launch");
+  for (long k = (long)M - 1; k >= 0; --k) {
+    const char* sl = store + (2 * k + 1) * slot;
+    if (c->g.dim == 2) {
+      e = run_colpass_ex<T>(c, C_ADJ, 1, lam, tab[k], lin[k], nullptr, sl);
+    } else {
+      // adjoint of (Y1 forward, Z, Y2 inverse): Y forward, Z adjoint, Y inverse
+      e = run_colpass_ex<T>(c, C_FWD, 1, lam, tab[k], lin[k], nullptr, nullptr);
+      if (e == hipSuccess) e = run_colpass_ex<T>(c, C_ADJ, 2, lam, tab[k], lin[k], nullptr, sl);
+      if (e == hipSuccess) e = run_colpass_ex<T>(c, C_INV, 1, lam, tab[k], lin[k], nullptr, nullptr);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint linear pass launch");
+    e = run_xpass_ex<T>(c, k == 0 ? XA_FIRST : XA_MID, lam, nl[k], CLOCK_ARG, s[k], nullptr, store + 2 * k * slot);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint X-pass launch");
+  }
+  return SGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -471,6 +570,12 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   long maxb = 0;
   for (int axis = 0; axis < c->g.dim; ++axis) maxb = std::max(maxb, obs_nblocks(c, axis));
   off += align256(sizeof(double) * NOBS * maxb);
+  // adjoint parameter slots: one per block of the largest pass
+  long gb = 0;
+  for (int axis = 0; axis < c->g.dim; ++axis) gb = std::max(gb, obs_nblocks(c, axis));
+  c->ngacc = gb;
+  c->off_gacc = off;
+  off += align256(sizeof(double) * NGRAD * gb);
   c->total = off;
   *out = c;
   return SGP_OK;
@@ -491,6 +596,8 @@ int sgp_set_workspace(sgp_ctx* c, void* dev_ptr, size_t bytes) {
   c->have_prop = false;
   drop_graph(c);
   hipError_t e = c->dtype == SGP_C64 ? upload_twiddles<float>(c) : upload_twiddles<double>(c);
+  if (e == hipSuccess) e = hipMemsetAsync(c->at(c->off_gacc), 0, sizeof(double) * NGRAD * c->ngacc, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) return hip_fail(c, e, "twiddle upload");
   return SGP_OK;
 }
@@ -564,6 +671,59 @@ int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
   return c->dtype == SGP_C64 ? time_pass_impl<float>(c, psi, pass, reps, avg_ms)
                              : time_pass_impl<double>(c, psi, pass, reps, avg_ms);
+}
+
+int sgp_store_size(const sgp_ctx* c, long nsteps, size_t* bytes) {
+  if (!c || !bytes || nsteps < 1) return SGP_ERR_ARG;
+  if (c->scheme == 0) return SGP_ERR_STATE;
+  const long M = (c->scheme == SGP_TS2 ? 1 : 3) * nsteps;
+  *bytes = (size_t)(2 * M + 1) * (size_t)c->npts() * 5 * 2 * c->esize;
+  return SGP_OK;
+}
+
+int sgp_step_store(sgp_ctx* c, void* psi, long nsteps, void* store, size_t store_bytes) {
+  if (!c || !psi || !store) return fail(c, SGP_ERR_ARG, "null argument");
+  if (nsteps < 1) return fail(c, SGP_ERR_ARG, "nsteps must be >= 1");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  size_t need = 0;
+  sgp_store_size(c, nsteps, &need);
+  if (store_bytes < need) return fail(c, SGP_ERR_WORKSPACE, "store too small");
+  return c->dtype == SGP_C64 ? step_store_impl<float>(c, psi, nsteps, (char*)store)
+                             : step_store_impl<double>(c, psi, nsteps, (char*)store);
+}
+
+int sgp_adjoint_segment(sgp_ctx* c, void* lam, long nsteps, const void* store, size_t store_bytes) {
+  if (!c || !lam || !store) return fail(c, SGP_ERR_ARG, "null argument");
+  if (nsteps < 1) return fail(c, SGP_ERR_ARG, "nsteps must be >= 1");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  size_t need = 0;
+  sgp_store_size(c, nsteps, &need);
+  if (store_bytes < need) return fail(c, SGP_ERR_WORKSPACE, "store too small");
+  return c->dtype == SGP_C64 ? adjoint_impl<float>(c, lam, nsteps, (const char*)store)
+                             : adjoint_impl<double>(c, lam, nsteps, (const char*)store);
+}
+
+int sgp_adjoint_gradients(sgp_ctx* c, double out[5], int reset) {
+  if (!c || !out) return fail(c, SGP_ERR_ARG, "null argument");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  std::vector<double> host((size_t)c->ngacc * NGRAD);
+  double* dev = (double*)c->at(c->off_gacc);
+  hipError_t e = hipMemcpyAsync(host.data(), dev, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return hip_fail(c, e, "gradient readback");
+  for (int q = 0; q < NGRAD; ++q) {
+    double acc = 0.0;
+    for (long b = 0; b < c->ngacc; ++b) acc += host[(size_t)b * NGRAD + q];
+    out[q] = acc;
+  }
+  if (reset) {
+    e = hipMemsetAsync(dev, 0, sizeof(double) * host.size(), c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "gradient reset");
+  }
+  return SGP_OK;
 }
 
 int sgp_set_option(sgp_ctx* c, int option, long value) {

@@ -470,4 +470,151 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
   for (int i = 0; i < 5; ++i) p[i] = b[i];
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the nonlinear flow at one point (real-linear, Wirtinger form).
+// Convention: a gradient g of a real loss J with respect to psi is 2 dJ/d conj(psi),
+// i.e. dJ = Re sum conj(g) dpsi.  With psi' = exp(-i phi) R b (see nl_point),
+// h = exp(i phi) R^H g' and k = -i Sigma h (Sigma = sin(c2 S d)/S, C = cos(c2 S d)):
+//   g = C h + (rho/5) k - A00 A conj(k) + 2 c_rho psi + 2 (c_F.f) psi + 2 conj(z) A conj(psi)
+// where the scalar sensitivities collect the dependence through rho, F, A00, S^2:
+//   q_phi = Im(g'^H psi'), m_a = Im(h^H f_a b), M = J_r(omega)^T m (omega = c1 d F,
+//   J_r the right Jacobian of the rotation exponential), q_C = Re(h^H psi),
+//   q_Sig = -Im(h^H w), q_w = Re(k^H psi)/5, z_w = -k^H A conj(psi),
+//   q_S = C'(S^2) q_C + Sigma'(S^2) q_Sig,
+//   c_rho = d c0' q_phi + q_w + q_S 2 rho/25, z = z_w - q_S (2/5) conj(A00), c_F = c1 d M.
+// Parameter partials (added to acc): dJ/dOmega (through the rotated trap, dVdO),
+// dJ/dc0, dJ/dc1, dJ/dc2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5], double V, double dVdO,
+                                             const NLCoef& K, double (&acc)[4]) {
+  const T r6 = T(2.44948974278317809819728407470589139);
+  const T r5i = T(0.44721359549995793928183473374625524);
+  const T w4[4] = {T(1), T(1.22474487139158904909864203735294570), T(1.22474487139158904909864203735294570), T(1)};
+  const T ml[5] = {T(2), T(1), T(0), T(-1), T(-2)};
+  const T n0 = norm2(p[0]), n1 = norm2(p[1]), n2 = norm2(p[2]), n3 = norm2(p[3]), n4 = norm2(p[4]);
+  const T rho = n0 + n1 + n2 + n3 + n4;
+  const T Fz = T(2) * (n0 - n4) + (n1 - n3);
+  const cx<T> Fp = T(2) * (cmulc(p[0], p[1]) + cmulc(p[3], p[4])) + r6 * (cmulc(p[1], p[2]) + cmulc(p[2], p[3]));
+  const cx<T> A00 = r5i * (T(2) * (p[0] * p[4] - p[1] * p[3]) + p[2] * p[2]);
+  const T rho5 = rho * T(0.2);
+  T S2 = rho5 * rho5 - norm2(A00) * T(0.2);
+  S2 = S2 > T(0) ? S2 : T(0);
+  const T S = sqrt(S2);
+  const T c2d = T(K.c2 * K.d);
+  T cm1, snc;
+  cosm1_sinc<T>(c2d * S, cm1, snc);
+  const T C = T(1) + cm1;
+  const T Sig = c2d * snc;
+  // Sigma'(S^2) = (c2 d C - Sigma)/(2 S^2), series -(c2 d)^3/6 (1 - x^2/10) for small x = c2 d S
+  const T x2 = c2d * c2d * S2;
+  const T Sigp = x2 < (sizeof(T) == 4 ? T(1e-3) : T(1e-6)) ? -(c2d * c2d * c2d) / T(6) * (T(1) - x2 / T(10))
+                                                           : (c2d * C - Sig) / (T(2) * S2);
+  const T Cp = -T(0.5) * c2d * Sig;
+  cx<T> Ab[5], w[5], b[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    cx<T> ab = conj(p[4 - i]);
+    if (i & 1) ab = mk<T>(-ab.re, -ab.im);
+    Ab[i] = r5i * ab;  // (A conj psi)_i
+    w[i] = rho5 * p[i] - A00 * Ab[i];
+    b[i] = p[i] + (cm1 * p[i] + Sig * mul_i(w[i]));
+  }
+  // rotation and phase (as in nl_point)
+  const T Fabs = sqrt(norm2(Fp) + Fz * Fz);
+  const T hc1d = T(0.5 * K.c1 * K.d);
+  T ckm1, skc;
+  cosm1_sinc<T>(hc1d * Fabs, ckm1, skc);
+  const T sr = hc1d * skc;
+  const cx<T> as = mk<T>(ckm1, -sr * Fz);
+  const cx<T> beta = mk<T>(-sr * Fp.im, -sr * Fp.re);
+  const double phi = K.d * (V + K.c0p * (double)rho);
+  const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
+  const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
+  double sd, cd, sh, chh;
+  sincos(red, &sd, &cd);
+  sincos(0.5 * red, &sh, &chh);
+  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-sd));
+  // psi' and h = exp(i phi) R^H g'
+  cx<T> out[5], h[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) { out[i] = b[i]; h[i] = g[i]; }
+  sym4_apply_inc<T>(as, beta, phs, out);
+  sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(phs), h);
+  double qphi = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) qphi += (double)g[i].re * out[i].im - (double)g[i].im * out[i].re;
+  // m_a = Im(h^H f_a b)
+  cx<T> up = mk<T>(T(0), T(0)), um = mk<T>(T(0), T(0)), uz = mk<T>(T(0), T(0));
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    up = up + (T(2) * w4[l]) * cmulc(h[l], b[l + 1]);
+    um = um + (T(2) * w4[l]) * cmulc(h[l + 1], b[l]);
+  }
+#pragma unroll
+  for (int l = 0; l < 5; ++l) uz = uz + ml[l] * cmulc(h[l], b[l]);
+  const T mx = T(0.5) * (up.im + um.im);
+  const T my = -T(0.5) * (up.re - um.re);
+  const T mz = uz.im;
+  // M = J_r(omega)^T m = m + a (omega x m) + bb (omega x (omega x m))
+  const T c1d = T(K.c1 * K.d);
+  const T ox = c1d * Fp.re, oy = c1d * Fp.im, oz = c1d * Fz;  // F_x = Re F_+, F_y = Im F_+
+  const T th2 = ox * ox + oy * oy + oz * oz;
+  T ja, jb;
+  if (th2 < (sizeof(T) == 4 ? T(1e-4) : T(1e-8))) {
+    ja = T(0.5) - th2 / T(24);
+    jb = T(1) / T(6) - th2 / T(120);
+  } else {
+    const T th = sqrt(th2);
+    T sth, cth;
+    if constexpr (sizeof(T) == 4) sincosf(th, &sth, &cth);
+    else sincos(th, &sth, &cth);
+    const T hs = sizeof(T) == 4 ? sinf(T(0.5) * th) : sin(T(0.5) * th);
+    ja = T(2) * hs * hs / th2;
+    jb = (th - sth) / (th2 * th);
+  }
+  const T cx1 = oy * mz - oz * my, cy1 = oz * mx - ox * mz, cz1 = ox * my - oy * mx;
+  const T cx2 = oy * cz1 - oz * cy1, cy2 = oz * cx1 - ox * cz1, cz2 = ox * cy1 - oy * cx1;
+  const T Mx = mx + ja * cx1 + jb * cx2, My = my + ja * cy1 + jb * cy2, Mz = mz + ja * cz1 + jb * cz2;
+  // sensitivities through b
+  T qC = T(0), qSig = T(0);
+  cx<T> k[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const cx<T> hp = cmulc(h[i], p[i]);
+    const cx<T> hw = cmulc(h[i], w[i]);
+    qC += hp.re;
+    qSig -= hw.im;
+    k[i] = mk<T>(Sig * h[i].im, -Sig * h[i].re);  // -i Sigma h
+  }
+  T qw = T(0);
+  cx<T> zw = mk<T>(T(0), T(0));
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    qw += cmulc(k[i], p[i]).re;
+    zw = zw - cmulc(k[i], Ab[i]);
+  }
+  qw *= T(0.2);
+  const T qS = Cp * qC + Sigp * qSig;
+  const T crho = T(K.d * K.c0p * qphi) + qw + qS * (T(2) * rho / T(25));
+  const cx<T> z = zw - (T(0.4) * qS) * conj(A00);
+  const T cFx = c1d * Mx, cFy = c1d * My, cFz = c1d * Mz;
+  const cx<T> cpm = mk<T>(cFx, -cFy), cpp = mk<T>(cFx, cFy);  // c_Fx -/+ i c_Fy
+  const cx<T> zc2 = T(2) * conj(z);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    cx<T> ak = conj(k[4 - i]);
+    if (i & 1) ak = mk<T>(-ak.re, -ak.im);
+    cx<T> r = C * h[i] + rho5 * k[i] - A00 * (r5i * ak) + (T(2) * crho) * p[i] + zc2 * Ab[i];
+    cx<T> fpsi = (cFz * ml[i]) * p[i];
+    if (i < 4) fpsi = fpsi + w4[i] * (cpm * p[i + 1]);
+    if (i > 0) fpsi = fpsi + w4[i - 1] * (cpp * p[i - 1]);
+    g[i] = r + T(2) * fpsi;
+  }
+  acc[0] += K.d * dVdO * qphi;                                                  // Omega (trap)
+  acc[1] += K.d * (double)rho * qphi;                                           // c0
+  acc[2] += K.d * ((double)Fp.re * Mx + (double)Fp.im * My + (double)Fz * Mz);  // c1
+  acc[3] += K.d * (double)rho5 * qphi + (double)(-(T)K.d * S2 * Sig) * qC + (double)((T)K.d * C) * qSig;  // c2
+}
+
 }  // namespace sgp

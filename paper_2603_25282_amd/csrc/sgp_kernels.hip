@@ -49,13 +49,17 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
   constexpr int TL = N / E;
   constexpr int NT = W * 5 * TL;
   constexpr int LS = PadLine<N>::size;
-  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY;
-  constexpr bool PW = XL || KIND == C_PROP;  // has a pointwise stage
+  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
+                      KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  constexpr bool ADJ = XADJ || KIND == C_ADJ;
+  constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
   constexpr int TILE = PW ? W * N * 5 : 0;
   constexpr int XCH = W * 5 * LS;
   constexpr int BUF = TILE > XCH ? TILE : XCH;
   __shared__ T lre[BUF];
   __shared__ T lim[BUF];
+  __shared__ double gred[ADJ ? NT / 64 + 1 : 1][NGRAD];
 
   const int tid = threadIdx.x;
   const int c = tid % 5;
@@ -98,8 +102,19 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
   const cx<T>* twf = reinterpret_cast<const cx<T>*>(a.tw_fwd);
   const cx<T>* twi = reinterpret_cast<const cx<T>*>(a.tw_inv);
 
-  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
-  if constexpr (KIND == C_PROP || KIND == C_FWD) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID)
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+
+  // forward store mode: keep the pointwise-stage input for the adjoint
+  if constexpr (PW && !ADJ) {
+    if (a.store != nullptr && active) {
+      cx<T>* st = reinterpret_cast<cx<T>*>(a.store);
+#pragma unroll
+      for (int m = 0; m < E; ++m) st[base + (long)(t + TL * m) * estride + c] = v[0][m];
+    }
+  }
+  double gacc[NGRAD] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
   if constexpr (PW) {
     // to the tile: point (col, j) component c at (col * N + j) * 5 + c
@@ -130,7 +145,25 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
         cx<T> p[5];
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) p[cc] = mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
-        nl_point<T>(p, V, K);
+        if constexpr (XADJ) {
+          // forward input of this nonlinear substep at the point, from the store
+          const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + (line < a.nlines ? line : 0) * (long)N * 5 + j * 5;
+          cx<T> q[5];
+#pragma unroll
+          for (int cc = 0; cc < 5; ++cc) q[cc] = fw[cc];
+          // dV/dOmega = s (gx^2 - gy^2) X Y (trap at R(Omega s) x)
+          const double dVdO = a.s_arg * (a.g2[0] - a.g2[1]) * X * Y;
+          double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+          nl_point_adj<T>(q, p, V, dVdO, K, acc4);
+          if (line < a.nlines) {
+            gacc[1] += acc4[0];
+            gacc[2] += acc4[1];
+            gacc[3] += acc4[2];
+            gacc[4] += acc4[3];
+          }
+        } else {
+          nl_point<T>(p, V, K);
+        }
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
       }
@@ -169,7 +202,49 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
         cx<T> p[5];
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) p[cc] = norm * mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
-        sym4_apply_inc<T>(as, beta, ss, p);
+        if constexpr (KIND == C_ADJ) {
+          // P^H = P(-d): same (C - 1), S -> -S, conjugate kinetic phase
+          sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
+          if (kx0 + pc < a.ncols) {
+            // m_a = -d Im(L^H f_a H), L = P^H L'/N^d (p), H the stored forward input
+            const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + o * a.outer_stride + kx * 5 + (long)kl * a.stride;
+            const double w4[4] = {1.0, 1.22474487139158904909864203735294570, 1.22474487139158904909864203735294570, 1.0};
+            double upr = 0, upi = 0, umr = 0, umi = 0, uzi = 0;
+            cx<T> hq[5];
+#pragma unroll
+            for (int cc = 0; cc < 5; ++cc) hq[cc] = fw[cc];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              const cx<T> a1 = cmulc(p[l], hq[l + 1]), a2 = cmulc(p[l + 1], hq[l]);
+              upr += 2.0 * w4[l] * a1.re; upi += 2.0 * w4[l] * a1.im;
+              umr += 2.0 * w4[l] * a2.re; umi += 2.0 * w4[l] * a2.im;
+            }
+#pragma unroll
+            for (int l = 0; l < 5; ++l) uzi += (2 - l) * (double)cmulc(p[l], hq[l]).im;
+            const double dd = a.d;
+            const double mx = -dd * 0.5 * (upi + umi);
+            const double my = dd * 0.5 * (upr - umr);
+            const double mz = -dd * uzi;
+            // dJ/dn = J_r(-d n)^T m, n = (gamma Re a, -gamma Im a, -Omega), a = -nu_q - i nu_p
+            const double nupd = px * a.nu_scale_a, nuqd = pq * a.nu_scale_q;
+            const double ox = -dd * a.gamma * (-nuqd), oy = -dd * (-a.gamma) * (-nupd), oz = -dd * (-a.Omega);
+            const double th2 = ox * ox + oy * oy + oz * oz;
+            double ja, jb;
+            if (th2 < 1e-8) { ja = 0.5 - th2 / 24.0; jb = 1.0 / 6.0 - th2 / 120.0; }
+            else {
+              const double th = sqrt(th2), hs = sin(0.5 * th);
+              ja = 2.0 * hs * hs / th2;
+              jb = (th - sin(th)) / (th2 * th);
+            }
+            const double cx1 = oy * mz - oz * my, cy1 = oz * mx - ox * mz, cz1 = ox * my - oy * mx;
+            const double cx2 = oy * cz1 - oz * cy1, cy2 = oz * cx1 - ox * cz1, cz2 = ox * cy1 - oy * cx1;
+            const double Dx = mx + ja * cx1 + jb * cx2, Dy = my + ja * cy1 + jb * cy2, Dz = mz + ja * cz1 + jb * cz2;
+            gacc[0] += -nuqd * Dx + nupd * Dy;  // dn/dgamma = (Re a, -Im a, 0) = (-nu_q, nu_p, 0)
+            gacc[1] += -Dz;                     // dn/dOmega = (0, 0, -1)
+          }
+        } else {
+          sym4_apply_inc<T>(as, beta, ss, p);
+        }
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
       }
@@ -183,14 +258,32 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
     __syncthreads();
   }
 
-  if constexpr (KIND == X_FIRST || KIND == X_MID) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
-  if constexpr (KIND == C_PROP) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+  if constexpr (KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST)
+    fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+  if constexpr (KIND == C_PROP || KIND == C_ADJ) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+
+  if constexpr (ADJ) {
+    // parameter partials: block reduction in a fixed order into this block's slot
+#pragma unroll
+    for (int q = 0; q < NGRAD; ++q) {
+      double vq = gacc[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) vq += __shfl_down(vq, off, 64);
+      if ((tid & 63) == 0) gred[tid >> 6][q] = vq;
+    }
+    __syncthreads();
+    if (tid < NGRAD) {
+      double sum = 0.0;
+      for (int wv = 0; wv < (NT + 63) / 64; ++wv) sum += gred[wv][tid];
+      a.gacc[(long)blockIdx.x * NGRAD + tid] += sum;
+    }
+  }
 
   if (active) {
 #pragma unroll
     for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
   }
-  if constexpr (XL) {
+  if constexpr (XL && !ADJ) {
     if (a.clock_mode == CLOCK_ARG && blockIdx.x == 0 && tid == 0) a.clock[0] = a.s_arg;
   }
   if constexpr (KIND == C_PROP) {
@@ -440,7 +533,8 @@ int lines_per_block(int n, bool xline, int esize) {
 template <typename T, int N, int KIND>
 static hipError_t pass_n(cx<T>* psi, const PassArgs& a, hipStream_t st) {
   constexpr int E = Geo<T, N>::E;
-  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY;
+  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
+                      KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
   constexpr int W = XL ? Geo<T, N>::WX : Geo<T, N>::WC;
   constexpr int NT = W * 5 * (N / E);
   long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
@@ -458,6 +552,10 @@ static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t
     case C_PROP: return pass_n<T, N, C_PROP>(psi, a, st);
     case C_FWD: return pass_n<T, N, C_FWD>(psi, a, st);
     case C_INV: return pass_n<T, N, C_INV>(psi, a, st);
+    case XA_FIRST: return pass_n<T, N, XA_FIRST>(psi, a, st);
+    case XA_MID: return pass_n<T, N, XA_MID>(psi, a, st);
+    case XA_LAST: return pass_n<T, N, XA_LAST>(psi, a, st);
+    case C_ADJ: return pass_n<T, N, C_ADJ>(psi, a, st);
     default: return hipErrorInvalidValue;
   }
 }

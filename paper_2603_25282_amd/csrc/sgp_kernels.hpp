@@ -4,7 +4,11 @@
 
 namespace sgp {
 
-enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, C_INV = 6 };
+enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, C_INV = 6,
+       // adjoints: of X_FIRST (iFFT, NL adjoint), of X_MID (iFFT, NL adjoint, FFT),
+       // of X_LAST (NL adjoint, FFT), of C_PROP (FFT, P^H and parameter partials, iFFT)
+       XA_FIRST = 7, XA_MID = 8, XA_LAST = 9, C_ADJ = 10 };
+enum { NGRAD = 5 };  // adjoint parameter slots: gamma, Omega, c0, c1, c2
 enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2 };
 enum { CLOCK_ARG = 0, CLOCK_DEVICE = 1 };
 enum { NOBS = 8 };  // partial sums per block of the observables kernels
@@ -44,6 +48,10 @@ struct PassArgs {
   double s_arg;          // clock value passed by the host (CLOCK_ARG; then written to *clock)
   int clock_mode;
   int advance_clock;
+  // adjoint support
+  void* store;           // forward: where to write the pointwise-stage input (or null)
+  const void* fwd;       // adjoint: the stored pointwise-stage input of the forward pass
+  double* gacc;          // adjoint: per-block parameter slots [block][NGRAD], accumulated
 };
 
 template <typename T>

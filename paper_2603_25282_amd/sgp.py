@@ -57,6 +57,10 @@ def lib():
     L.sgp_set_time.argtypes = [vp, ctypes.c_double]
     L.sgp_time_pass.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.sgp_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_long]
+    L.sgp_store_size.argtypes = [vp, ctypes.c_long, ctypes.POINTER(ctypes.c_size_t)]
+    L.sgp_step_store.argtypes = [vp, vp, ctypes.c_long, vp, ctypes.c_size_t]
+    L.sgp_adjoint_segment.argtypes = [vp, vp, ctypes.c_long, vp, ctypes.c_size_t]
+    L.sgp_adjoint_gradients.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.sgp_destroy.argtypes = [vp]
     L.sgp_destroy.restype = None
     L.sgp_last_error.argtypes = [vp]
@@ -69,7 +73,7 @@ def exported_symbols():
     """Names of the C-ABI entry points this binding expects (all declared in sgp.h)."""
     return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
-            "sgp_last_error"]
+            "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients"]
 
 
 def _check(rc, ctx=None):
@@ -156,6 +160,30 @@ class Solver:
         _check(lib().sgp_time_pass(self._ctx, self._psi_ptr(psi), int(pass_kind), int(reps), ctypes.byref(ms)),
                self._ctx)
         return ms.value
+
+    def store_size(self, nsteps):
+        nb = ctypes.c_size_t()
+        _check(lib().sgp_store_size(self._ctx, int(nsteps), ctypes.byref(nb)), self._ctx)
+        return int(nb.value)
+
+    def step_store(self, psi, nsteps, store):
+        """sgp_step_store: forward nsteps, keeping every pass's pointwise-stage input in
+        `store` (a uint8 device tensor of at least store_size(nsteps) bytes)."""
+        _check(lib().sgp_step_store(self._ctx, self._psi_ptr(psi), int(nsteps), ctypes.c_void_p(store.data_ptr()),
+                                    store.numel() * store.element_size()), self._ctx)
+
+    def adjoint_segment(self, lam, nsteps, store):
+        """sgp_adjoint_segment: reverse sweep of the step_store call that started at the
+        current clock; lam is overwritten with the gradient at the segment start."""
+        _check(lib().sgp_adjoint_segment(self._ctx, self._psi_ptr(lam), int(nsteps),
+                                         ctypes.c_void_p(store.data_ptr()), store.numel() * store.element_size()),
+               self._ctx)
+
+    def adjoint_gradients(self, reset=True):
+        """dJ/d(gamma, Omega, c0, c1, c2) accumulated by adjoint_segment calls."""
+        out = (ctypes.c_double * 5)()
+        _check(lib().sgp_adjoint_gradients(self._ctx, out, int(bool(reset))), self._ctx)
+        return np.array(out[:])
 
     def set_graph(self, on):
         _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)

@@ -1,0 +1,97 @@
+"""GPU adjoint (C ABI sgp_step_store / sgp_adjoint_segment and the autograd
+Function) against the FP64 oracle's discrete adjoint and against finite differences
+of the GPU forward.  Gradient convention: 2 dJ/d conj(psi)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_25282_amd import inputs as I
+from tests.adjoint_loss import loss_and_grad
+from tests.gpu_util import rel_l2
+from tests.test_oracle_scheme import smooth_state
+
+pytestmark = pytest.mark.gpu
+
+PIDX = [4, 3, 0, 1, 2]  # (gamma, Omega, c0, c1, c2) in the params tuple
+
+
+def gpu_adjoint(psi0, gT, L, params, order, tau, n, K, dtype):
+    import torch
+    from paper_2603_25282_amd.autograd import evolve
+    from paper_2603_25282_amd.sgp import Solver
+    dev = torch.device("cuda:0")
+    tdt = torch.complex64 if dtype == "complex64" else torch.complex128
+    p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(tdt).to(dev).requires_grad_(True)
+    par = torch.tensor([params[i] for i in PIDX], dtype=torch.float64, requires_grad=True)
+    out = evolve(p0, par, psi0.shape[1:], L, params[5:8], tau, n, order=order, K=K)
+    g = torch.from_numpy(Solver.to_device_layout(gT)).to(tdt).to(dev)
+    # J = Re sum conj(gT) phi_T  ->  dJ = Re <gT, dphi>, so the incoming gradient is gT
+    J = torch.sum((torch.conj(g) * out).real)
+    J.backward()
+    g0 = Solver.from_device_layout(p0.grad.cpu().numpy().astype(np.complex128))
+    return g0, par.grad.numpy(), Solver.from_device_layout(out.detach().cpu().numpy().astype(np.complex128))
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_adjoint_matches_oracle_adjoint(dtype, order):
+    params = (60.0, -2.0, 3.0, 0.7, 0.9, 1.0, 1.2, 1.0)
+    L, shape = 6.0, (32, 32)
+    psi = smooth_state(shape, L, 21, lz=0.3)
+    w = np.random.default_rng(5).standard_normal(psi.shape) + 1j * np.random.default_rng(6).standard_normal(psi.shape)
+    tau, n = 4e-3, 7
+    print(f"case adjoint 32^2 {dtype} TS{order}", flush=True)
+    g_ref, d_ref = oracle.adjoint(psi, w, L, params, order, tau, n, K=3)
+    g, d, _ = gpu_adjoint(psi, w, L, params, order, tau, n, K=3, dtype=dtype)
+    eg = rel_l2(g, g_ref)
+    ed = np.abs(d - d_ref) / np.maximum(1.0, np.abs(d_ref))
+    print("state grad rel l2", eg, "param grads", d, "oracle", d_ref, "rel", ed)
+    tol = 1e-11 if dtype == "complex128" else 5e-5
+    assert eg <= tol
+    assert np.all(ed <= (1e-10 if dtype == "complex128" else 2e-4))
+
+
+def test_workload_loss_gradients_fd_and_oracle():
+    # The differentiation workload's loss on 64^2 with checkpoints: GPU FP64 adjoint vs
+    # oracle adjoint, and the GPU FP32 adjoint vs central finite differences of the
+    # GPU FP64 forward (relative 1e-4).
+    import torch
+    from paper_2603_25282_amd.autograd import evolve
+    from paper_2603_25282_amd.sgp import Solver
+    cfg = I.with_(I.C5, shape=(64, 64), L=8.0)
+    psi0 = I.initial_state(I.with_(cfg, init="gauss_phase"))
+    psi0 = smooth_state(cfg.shape, cfg.L, 41, lz=0.4)
+    target = smooth_state(cfg.shape, cfg.L, 42, lz=0.1)
+    tau, n, K = 1e-3, 12, 5
+    u = oracle.evolve(psi0, cfg.L, cfg.params, 4, tau, n)
+    J0, gT = loss_and_grad(u, target, cfg.L)
+    g_ref, d_ref = oracle.adjoint(psi0, gT, cfg.L, cfg.params, 4, tau, n, K=K)
+    g64, d64, out64 = gpu_adjoint(psi0, gT, cfg.L, cfg.params, 4, tau, n, K, "complex128")
+    assert rel_l2(out64, u) < 1e-11
+    assert rel_l2(g64, g_ref) < 1e-10
+    assert np.all(np.abs(d64 - d_ref) <= 1e-9 * np.maximum(1.0, np.abs(d_ref)))
+
+    def J_gpu(p0, params):
+        s = Solver(cfg.shape, cfg.L, params, dtype="complex128")
+        s.build_propagator(tau, 4)
+        t = torch.from_numpy(Solver.to_device_layout(p0)).cuda()
+        s.step(t, n)
+        phi = Solver.from_device_layout(t.cpu().numpy())
+        return loss_and_grad(phi, target, cfg.L)[0]
+
+    g32, d32, _ = gpu_adjoint(psi0, gT, cfg.L, cfg.params, 4, tau, n, K, "complex64")
+    eps = 1e-6
+    rng = np.random.default_rng(9)
+    for _ in range(2):
+        v = rng.standard_normal(psi0.shape) + 1j * rng.standard_normal(psi0.shape)
+        fd = (J_gpu(psi0 + eps * v, cfg.params) - J_gpu(psi0 - eps * v, cfg.params)) / (2 * eps)
+        an = np.real(np.vdot(g32, v))
+        print("state direction fd", fd, "adjoint fp32", an)
+        assert abs(fd - an) <= 1e-4 * max(1e-3, abs(fd))
+    for k, i in enumerate(PIDX):
+        pp, pm = list(cfg.params), list(cfg.params)
+        pp[i] += eps
+        pm[i] -= eps
+        fd = (J_gpu(psi0, pp) - J_gpu(psi0, pm)) / (2 * eps)
+        print("param", k, "fd", fd, "adjoint fp32", d32[k], "fp64", d64[k])
+        assert abs(fd - d32[k]) <= 1e-4 * max(1e-3, abs(fd))
