@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=200)
+    ap.add_argument("--adjoint-steps", type=int, default=100,
+                    help="steps of the fwd+adjoint measurement (0 to skip)")
+    ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
     return ap.parse_args()
 
 
@@ -120,6 +123,31 @@ def main():
     # whole-step bandwidth of the bytes model (R round trips of the state per step)
     out["bytes_model"] = {"bytes_per_gp_step": sum(per_point[k] * launches_per_step[k] for k in passes),
                           "GB_per_s": sum(per_point[k] * launches_per_step[k] for k in passes) * gps / 1e9}
+
+    if a.adjoint_steps > 0:
+        # forward with checkpoints every K steps + backward (recompute with stores and
+        # reverse sweep), the loss gradient being a fixed random direction
+        from paper_2603_25282_amd.autograd import evolve
+        n_adj = a.adjoint_steps
+        p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).requires_grad_(True)
+        prm = cfg.params
+        par = torch.tensor([prm[4], prm[3], prm[0], prm[1], prm[2]], dtype=torch.float64, requires_grad=True)
+        gdir = torch.randn(p0.shape, dtype=s.torch_dtype, device=s.device)
+
+        def fwd_bwd():
+            out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, n_adj, order=cfg.order, K=a.K)
+            J = torch.sum((torch.conj(gdir) * out).real)
+            J.backward()
+
+        fwd_bwd()  # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd_bwd()
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        out["fwd_adjoint"] = {"metric": "5-comp grid-point-steps/s fwd+adjoint", "value": npts * n_adj / ta,
+                              "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj,
+                              "grad_finite": bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())}
 
     if not a.no_cpu_baseline:
         import oracle

@@ -155,7 +155,7 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
 
 /* Options.  SGP_OPT_GRAPH (default 1): replay the periodic part of sgp_step()
  * from a captured HIP graph (value 0 launches every kernel individually). */
-enum { SGP_OPT_GRAPH = 1 };
+enum { SGP_OPT_GRAPH = 1, SGP_OPT_BATCHED = 2 };
 int sgp_set_option(sgp_ctx* ctx, int option, long value);
 
 /* Release the context (not the caller's workspace or state). */
@@ -164,6 +164,31 @@ void sgp_destroy(sgp_ctx* ctx);
 /* Message of the last error on this context ("" if none); ctx may be NULL for
  * errors raised by sgp_create(). */
 const char* sgp_last_error(const sgp_ctx* ctx);
+
+/* ---- Ensembles of 2D grids -------------------------------------------------
+ * Many independent 2D instances (square grids with N in {64, 128, 256, 384, 512},
+ * each with its own domain and parameters, same element type and scheme) advanced
+ * together: every pass type of a step is one batched launch over the work list of
+ * all instances' line tiles, and the periodic part of a step is replayed from one
+ * HIP graph.  Each instance evolves exactly as with its own context (same kernels
+ * per line; results are bitwise identical). */
+typedef struct sgp_ensemble sgp_ensemble;
+
+int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* params, int dtype, void* hip_stream,
+                        sgp_ensemble** out);
+/* One caller-owned workspace for all instances (tables, twiddles, work lists). */
+int sgp_ensemble_workspace_size(const sgp_ensemble* ens, size_t* bytes);
+int sgp_ensemble_set_workspace(sgp_ensemble* ens, void* dev_ptr, size_t bytes);
+/* FP64 propagator tables of every instance for the common tau and scheme. */
+int sgp_ensemble_build_propagator(sgp_ensemble* ens, double tau, int scheme);
+/* psi_devs: host array of n_inst device pointers (instance i: [ny][nx][5] complex).
+ * Advances every instance by nsteps (common clock).  Asynchronous. */
+int sgp_ensemble_step(sgp_ensemble* ens, void* const* psi_devs, long nsteps);
+/* SGP_OPT_GRAPH (default 1) as for contexts; SGP_OPT_BATCHED (default 1): 0 runs
+ * every instance with its own launches (the unbatched reference). */
+int sgp_ensemble_set_option(sgp_ensemble* ens, int option, long value);
+void sgp_ensemble_destroy(sgp_ensemble* ens);
+const char* sgp_ensemble_last_error(const sgp_ensemble* ens);
 
 #ifdef __cplusplus
 }

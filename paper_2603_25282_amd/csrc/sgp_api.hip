@@ -29,7 +29,7 @@ std::vector<int> plan_of(bool fwd) {
   return fwd ? radix_list(typename Plan<N, E>::fwd{}) : radix_list(typename Plan<N, E>::inv{});
 }
 
-bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
+bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 384 || n == 512; }
 
 std::vector<int> plan_radices(int n, bool fwd) {
   switch (n) {
@@ -38,6 +38,7 @@ std::vector<int> plan_radices(int n, bool fwd) {
     case 64: return plan_of<64, 8>(fwd);
     case 128: return plan_of<128, 8>(fwd);
     case 256: return plan_of<256, 8>(fwd);
+    case 384: return plan_of<384, 12>(fwd);
     case 512: return plan_of<512, 8>(fwd);
     default: return {};
   }
@@ -744,5 +745,312 @@ void sgp_destroy(sgp_ctx* c) {
 }
 
 const char* sgp_last_error(const sgp_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"
+
+
+// ===========================================================================
+// Ensembles: many 2D grids (uneven sizes, own parameters) advanced together.
+// Each pass type of a step is ONE batched launch over the work list of all
+// instances' tiles; the periodic step body is replayed from a HIP graph.
+// ===========================================================================
+struct sgp_ensemble {
+  int n = 0;
+  int dtype = 0;
+  hipStream_t st = nullptr;
+  std::vector<sgp_ctx*> ctx;
+  std::vector<size_t> ws_off;
+  size_t total = 0;
+  size_t off_items_x = 0, off_items_y = 0, off_args = 0;
+  long nitems_x = 0, nitems_y = 0;
+  char* ws = nullptr;
+  int nslots = 0;  // PassArgs slots (per instance): see ens_slots()
+  std::vector<void*> psis;
+  bool args_ok = false;
+  bool use_graph = true;
+  bool batched = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gsteps = 0;
+  int scheme = 0;
+  double tau = 0.0;
+  double t = 0.0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_ens_err;
+
+int efail(sgp_ensemble* e, int code, const std::string& msg) {
+  if (e) e->err = msg;
+  else g_ens_err = msg;
+  return code;
+}
+
+// Argument slots of one step: 0 first X, 1 X (a2 or merged in TS2), 2 merged X (TS4),
+// 3 last X, 4 linear with table 0, 5 linear with table 1.
+enum { ES_XFIRST = 0, ES_XMID = 1, ES_XMERGE = 2, ES_XLAST = 3, ES_LIN0 = 4, ES_LIN1 = 5, ES_N = 6 };
+
+void drop_egraph(sgp_ensemble* e) {
+  if (e->gexec) hipGraphExecDestroy(e->gexec);
+  e->gexec = nullptr;
+  e->gsteps = 0;
+}
+
+// Build all PassArgs slots for the current state pointers and upload them.
+hipError_t ens_upload_args(sgp_ensemble* e) {
+  std::vector<PassArgs> host((size_t)ES_N * e->n);
+  const double tau = e->tau;
+  double dX[4], dL[2];
+  if (e->scheme == SGP_TS2) {
+    dX[0] = 0.5 * tau; dX[1] = tau; dX[2] = tau; dX[3] = 0.5 * tau;
+    dL[0] = tau; dL[1] = tau;
+  } else {
+    TS4 k;
+    dX[0] = k.a1 * tau; dX[1] = k.a2 * tau; dX[2] = 2.0 * k.a1 * tau; dX[3] = k.a1 * tau;
+    dL[0] = k.b1 * tau; dL[1] = k.b2 * tau;
+  }
+  for (int i = 0; i < e->n; ++i) {
+    sgp_ctx* c = e->ctx[i];
+    for (int sl = 0; sl < ES_N; ++sl) {
+      PassArgs a = base_args(c);
+      a.state = e->psis[i];
+      a.gacc = (double*)c->at(c->off_gacc);
+      if (sl <= ES_XLAST) {
+        a.tw_fwd = c->at(c->off_tw[0][0]);
+        a.tw_inv = c->at(c->off_tw[0][1]);
+        a.d = dX[sl];
+        a.clock_mode = sl == ES_XFIRST ? CLOCK_ARG : CLOCK_DEVICE;
+        a.s_arg = e->t;
+        a.n_line = c->g.n[0];
+      } else {
+        const int table = sl == ES_LIN0 ? 0 : (e->scheme == SGP_TS2 ? 0 : 1);
+        column_geometry(c, 1, a);
+        a.cs = c->at(c->off_cs[table]);
+        a.kin_a = c->at(c->off_kin[table][0]);
+        a.kin_o = c->at(c->off_kin[table][1]);
+        a.kin_l = c->at(c->off_kin[table][1]);
+        a.d = dL[sl - ES_LIN0];
+        a.advance_clock = 1;
+        a.n_line = c->g.n[1];
+      }
+      host[(size_t)sl * e->n + i] = a;
+    }
+  }
+  hipError_t r = hipMemcpyAsync(e->ws + e->off_args, host.data(), sizeof(PassArgs) * host.size(),
+                                hipMemcpyHostToDevice, e->st);
+  if (r == hipSuccess) r = hipStreamSynchronize(e->st);
+  return r;
+}
+
+template <typename T>
+hipError_t ens_launch(sgp_ensemble* e, hipStream_t st, int slot) {
+  const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
+  const bool xl = slot <= ES_XLAST;
+  const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
+  return launch_pass_batched<T>(kind, e->ws + (xl ? e->off_items_x : e->off_items_y), args,
+                                xl ? e->nitems_x : e->nitems_y, st);
+}
+
+// Slots of one body step (after a merged nonlinear substep, ending with the next one)
+// and of the final step.
+std::vector<int> ens_body(int scheme) {
+  if (scheme == SGP_TS2) return {ES_LIN0, ES_XMERGE};
+  return {ES_LIN0, ES_XMID, ES_LIN1, ES_XMID, ES_LIN0, ES_XMERGE};
+}
+std::vector<int> ens_tail(int scheme) {
+  if (scheme == SGP_TS2) return {ES_LIN0, ES_XLAST};
+  return {ES_LIN0, ES_XMID, ES_LIN1, ES_XMID, ES_LIN0, ES_XLAST};
+}
+
+template <typename T>
+int ens_step_impl(sgp_ensemble* e, long nsteps) {
+  hipError_t r = ens_launch<T>(e, e->st, ES_XFIRST);
+  if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
+  long nbody = nsteps - 1;
+  const int G = 16;
+  if (e->use_graph && nbody >= G) {
+    if (!e->gexec || e->gsteps != G) {
+      drop_egraph(e);
+      if (!e->cap && (r = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking)) != hipSuccess)
+        return efail(e, SGP_ERR_HIP, "stream create");
+      r = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
+      if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "graph capture");
+      hipError_t r1 = hipSuccess;
+      for (int b = 0; b < G && r1 == hipSuccess; ++b)
+        for (int sl : ens_body(e->scheme))
+          if (r1 == hipSuccess) r1 = ens_launch<T>(e, e->cap, sl);
+      hipGraph_t g = nullptr;
+      r = hipStreamEndCapture(e->cap, &g);
+      if (r1 != hipSuccess || r != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return efail(e, SGP_ERR_HIP, "graph capture");
+      }
+      r = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (r != hipSuccess) { e->gexec = nullptr; return efail(e, SGP_ERR_HIP, "graph instantiate"); }
+      e->gsteps = G;
+    }
+    for (long i = 0; i < nbody / G; ++i)
+      if ((r = hipGraphLaunch(e->gexec, e->st)) != hipSuccess) return efail(e, SGP_ERR_HIP, "graph launch");
+    nbody %= G;
+  }
+  for (long b = 0; b < nbody; ++b)
+    for (int sl : ens_body(e->scheme))
+      if ((r = ens_launch<T>(e, e->st, sl)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
+  for (int sl : ens_tail(e->scheme))
+    if ((r = ens_launch<T>(e, e->st, sl)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
+  return SGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* params, int dtype, void* hip_stream,
+                        sgp_ensemble** out) {
+  if (!grids || !params || !out || n_inst < 1) return efail(nullptr, SGP_ERR_ARG, "bad argument");
+  *out = nullptr;
+  sgp_ensemble* e = new (std::nothrow) sgp_ensemble();
+  if (!e) return efail(nullptr, SGP_ERR_ARG, "out of host memory");
+  e->n = n_inst;
+  e->dtype = dtype;
+  e->st = (hipStream_t)hip_stream;
+  size_t off = 0;
+  std::vector<int2> items_x, items_y;
+  for (int i = 0; i < n_inst; ++i) {
+    if (grids[i].dim != 2 || grids[i].n[0] != grids[i].n[1] ||
+        (grids[i].n[0] != 64 && grids[i].n[0] != 128 && grids[i].n[0] != 256 && grids[i].n[0] != 384 &&
+         grids[i].n[0] != 512)) {
+      delete e;
+      return efail(nullptr, SGP_ERR_ARG, "ensemble grids must be 2D N x N with N in {64, 128, 256, 384, 512}");
+    }
+    sgp_ctx* c = nullptr;
+    int rc = sgp_create(&grids[i], &params[i], dtype, hip_stream, &c);
+    if (rc != SGP_OK) {
+      std::string m = sgp_last_error(nullptr);
+      for (auto* cc : e->ctx) sgp_destroy(cc);
+      delete e;
+      return efail(nullptr, rc, "instance " + std::to_string(i) + ": " + m);
+    }
+    e->ctx.push_back(c);
+    e->ws_off.push_back(off);
+    off += align256(c->total);
+    const int N = grids[i].n[0];
+    const int W = batched_lines_per_block(N);
+    const int ntiles = (N + W - 1) / W;  // x-lines: ny lines; columns: nx columns (nouter = 1)
+    for (int tIdx = 0; tIdx < ntiles; ++tIdx) {
+      items_x.push_back(make_int2(i, tIdx));
+      items_y.push_back(make_int2(i, tIdx));
+    }
+  }
+  e->nitems_x = (long)items_x.size();
+  e->nitems_y = (long)items_y.size();
+  e->off_items_x = off;
+  off += align256(sizeof(int2) * items_x.size());
+  e->off_items_y = off;
+  off += align256(sizeof(int2) * items_y.size());
+  e->off_args = off;
+  off += align256(sizeof(PassArgs) * ES_N * n_inst);
+  e->total = off;
+  e->psis.assign(n_inst, nullptr);
+  *out = e;
+  return SGP_OK;
+}
+
+int sgp_ensemble_workspace_size(const sgp_ensemble* e, size_t* bytes) {
+  if (!e || !bytes) return SGP_ERR_ARG;
+  *bytes = e->total;
+  return SGP_OK;
+}
+
+int sgp_ensemble_set_workspace(sgp_ensemble* e, void* dev_ptr, size_t bytes) {
+  if (!e || !dev_ptr) return efail(e, SGP_ERR_ARG, "null argument");
+  if (bytes < e->total) return efail(e, SGP_ERR_WORKSPACE, "workspace too small");
+  if (((uintptr_t)dev_ptr) & 255) return efail(e, SGP_ERR_ARG, "workspace must be 256-byte aligned");
+  e->ws = (char*)dev_ptr;
+  for (int i = 0; i < e->n; ++i) {
+    int rc = sgp_set_workspace(e->ctx[i], e->ws + e->ws_off[i], e->ctx[i]->total);
+    if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);
+  }
+  std::vector<int2> items;
+  for (int i = 0; i < e->n; ++i) {
+    const int N = e->ctx[i]->g.n[0];
+    const int W = batched_lines_per_block(N);
+    for (int tIdx = 0; tIdx < (N + W - 1) / W; ++tIdx) items.push_back(make_int2(i, tIdx));
+  }
+  hipError_t r = hipMemcpyAsync(e->ws + e->off_items_x, items.data(), sizeof(int2) * items.size(),
+                                hipMemcpyHostToDevice, e->st);
+  if (r == hipSuccess)
+    r = hipMemcpyAsync(e->ws + e->off_items_y, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice,
+                       e->st);
+  if (r == hipSuccess) r = hipStreamSynchronize(e->st);
+  if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "work list upload");
+  e->args_ok = false;
+  drop_egraph(e);
+  return SGP_OK;
+}
+
+int sgp_ensemble_build_propagator(sgp_ensemble* e, double tau, int scheme) {
+  if (!e) return SGP_ERR_ARG;
+  if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
+  for (int i = 0; i < e->n; ++i) {
+    int rc = sgp_build_propagator(e->ctx[i], tau, scheme);
+    if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);
+  }
+  e->scheme = scheme;
+  e->tau = tau;
+  e->args_ok = false;
+  drop_egraph(e);
+  return SGP_OK;
+}
+
+int sgp_ensemble_step(sgp_ensemble* e, void* const* psi_devs, long nsteps) {
+  if (!e || !psi_devs) return efail(e, SGP_ERR_ARG, "null argument");
+  if (nsteps < 0) return efail(e, SGP_ERR_ARG, "nsteps must be >= 0");
+  if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
+  if (e->scheme == 0) return efail(e, SGP_ERR_STATE, "propagator not built");
+  if (nsteps == 0) return SGP_OK;
+  for (int i = 0; i < e->n; ++i)
+    if (!psi_devs[i]) return efail(e, SGP_ERR_ARG, "null state pointer");
+  if (!e->batched) {
+    for (int i = 0; i < e->n; ++i) {
+      e->ctx[i]->t = e->t;
+      int rc = sgp_step(e->ctx[i], psi_devs[i], nsteps);
+      if (rc != SGP_OK) return efail(e, rc, e->ctx[i]->err);
+    }
+    e->t += nsteps * e->tau;
+    return SGP_OK;
+  }
+  bool same = e->args_ok;
+  for (int i = 0; i < e->n && same; ++i) same = e->psis[i] == psi_devs[i];
+  // the first X-pass of a call carries the current clock: re-upload every call
+  e->psis.assign(psi_devs, psi_devs + e->n);
+  hipError_t r = ens_upload_args(e);
+  if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "argument upload");
+  if (!same) drop_egraph(e);
+  e->args_ok = true;
+  int rc = e->dtype == SGP_C64 ? ens_step_impl<float>(e, nsteps) : ens_step_impl<double>(e, nsteps);
+  if (rc == SGP_OK) e->t += nsteps * e->tau;
+  return rc;
+}
+
+int sgp_ensemble_set_option(sgp_ensemble* e, int option, long value) {
+  if (!e) return SGP_ERR_ARG;
+  if (option == SGP_OPT_GRAPH) { e->use_graph = value != 0; drop_egraph(e); return SGP_OK; }
+  if (option == SGP_OPT_BATCHED) { e->batched = value != 0; return SGP_OK; }
+  return efail(e, SGP_ERR_ARG, "unknown option");
+}
+
+void sgp_ensemble_destroy(sgp_ensemble* e) {
+  if (!e) return;
+  drop_egraph(e);
+  if (e->cap) hipStreamDestroy(e->cap);
+  for (auto* c : e->ctx) sgp_destroy(c);
+  delete e;
+}
+
+const char* sgp_ensemble_last_error(const sgp_ensemble* e) { return e ? e->err.c_str() : g_ens_err.c_str(); }
 
 }  // extern "C"

@@ -44,22 +44,33 @@ __device__ __forceinline__ void trap_angle(const PassArgs& a, double& c, double&
 //   X_LAST:  iFFTx -> NL -> store phys              X_NLONLY: NL only
 //   C_PROP:  FFT -> propagator -> iFFT (column)     C_FWD / C_INV: FFT / iFFT only
 // ---------------------------------------------------------------------------
+template <int KIND> struct KindInfo {
+  static constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
+                             KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  static constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  static constexpr bool ADJ = XADJ || KIND == C_ADJ;
+  static constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
+};
+
+// LDS elements (per re / im array) a pass needs.
+template <int N, int W, int KIND>
+constexpr int pass_lds() {
+  constexpr int TILE = KindInfo<KIND>::PW ? W * N * 5 : 0;
+  constexpr int XCH = W * 5 * PadLine<N>::size;
+  return TILE > XCH ? TILE : XCH;
+}
+
+// Body of one block of a pass over `tile` (W lines), with caller-provided LDS.
 template <typename T, int N, int E, int W, int KIND>
-__global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ psi, PassArgs a) {
+__device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArgs& a, long tile, T* lre, T* lim,
+                                          double (*gred)[NGRAD]) {
   constexpr int TL = N / E;
   constexpr int NT = W * 5 * TL;
   constexpr int LS = PadLine<N>::size;
-  constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
-                      KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
-  constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
-  constexpr bool ADJ = XADJ || KIND == C_ADJ;
-  constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
-  constexpr int TILE = PW ? W * N * 5 : 0;
-  constexpr int XCH = W * 5 * LS;
-  constexpr int BUF = TILE > XCH ? TILE : XCH;
-  __shared__ T lre[BUF];
-  __shared__ T lim[BUF];
-  __shared__ double gred[ADJ ? NT / 64 + 1 : 1][NGRAD];
+  constexpr bool XL = KindInfo<KIND>::XL;
+  constexpr bool XADJ = KindInfo<KIND>::XADJ;
+  constexpr bool ADJ = KindInfo<KIND>::ADJ;
+  constexpr bool PW = KindInfo<KIND>::PW;
 
   const int tid = threadIdx.x;
   const int c = tid % 5;
@@ -68,7 +79,6 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
   // columns: the W columns are adjacent (W*5 contiguous values per row)
   const int col = XL ? rest / TL : rest % W;
   const int t = XL ? rest % TL : rest / W;
-  const long tile = xcd_tile(blockIdx.x, gridDim.x);
 
   // line geometry
   long base;        // element offset of the line's first point (component 0)
@@ -173,6 +183,8 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
       const cx<T>* kin_o = reinterpret_cast<const cx<T>*>(a.kin_o);
       const cx<T>* kin_l = reinterpret_cast<const cx<T>*>(a.kin_l);
       const T Om = T(a.Omega), ga = T(a.gamma), norm = T(a.norm);
+      // 1/N^d as a (hi, lo) pair: exact for powers of two, compensated otherwise
+      const T norm_lo = T(a.norm - (double)norm);
       const int nxx = (int)a.ncols;
       for (int pt = tid; pt < W * N; pt += NT) {
         const int pc = pt / N, kl = pt % N;
@@ -201,7 +213,8 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
         const cx<T> ss = ka + kl1 + ka * kl1;  // kinetic phase - 1
         cx<T> p[5];
 #pragma unroll
-        for (int cc = 0; cc < 5; ++cc) p[cc] = norm * mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
+        for (int cc = 0; cc < 5; ++cc)
+          p[cc] = mk<T>(kmul<T>(norm, norm_lo, lre[pt * 5 + cc]), kmul<T>(norm, norm_lo, lim[pt * 5 + cc]));
         if constexpr (KIND == C_ADJ) {
           // P^H = P(-d): same (C - 1), S -> -S, conjugate kinetic phase
           sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
@@ -284,10 +297,45 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
     for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
   }
   if constexpr (XL && !ADJ) {
-    if (a.clock_mode == CLOCK_ARG && blockIdx.x == 0 && tid == 0) a.clock[0] = a.s_arg;
+    if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) a.clock[0] = a.s_arg;
   }
   if constexpr (KIND == C_PROP) {
-    if (a.advance_clock && blockIdx.x == 0 && tid == 0) a.clock[0] += a.d;
+    if (a.advance_clock && tile == 0 && tid == 0) a.clock[0] += a.d;
+  }
+}
+
+template <typename T, int N, int E, int W, int KIND>
+__global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ psi, PassArgs a) {
+  constexpr int BUF = pass_lds<N, W, KIND>();
+  constexpr int NT = W * 5 * (N / E);
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double gred[KindInfo<KIND>::ADJ ? NT / 64 + 1 : 1][NGRAD];
+  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lre, lim, gred);
+}
+
+// ---------------------------------------------------------------------------
+// Batched pass over many grids (an ensemble): block b processes work item
+// items[b] = (instance, tile) with that instance's arguments; every line length
+// used runs with 320 threads per block (W = 64 E / N lines per block).
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
+  constexpr int BUF = pass_lds<384, 2, KIND>() > pass_lds<512, 1, KIND>() ? pass_lds<384, 2, KIND>()
+                                                                           : pass_lds<512, 1, KIND>();
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double gred[KindInfo<KIND>::ADJ ? 6 : 1][NGRAD];
+  const int2 it = items[blockIdx.x];
+  const PassArgs& a = args[it.x];
+  cx<T>* psi = reinterpret_cast<cx<T>*>(a.state);
+  switch (a.n_line) {
+    case 64: pass_body<T, 64, 8, 8, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 128: pass_body<T, 128, 8, 4, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 256: pass_body<T, 256, 8, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 384: pass_body<T, 384, 12, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 512: pass_body<T, 512, 8, 1, KIND>(psi, a, it.y, lre, lim, gred); break;
+    default: break;
   }
 }
 
@@ -512,22 +560,22 @@ __global__ void k_build_kin(cx<T>* __restrict__ kin, int n, double L, double d) 
 }
 
 // ---------------------------------------------------------------------------
-// Launchers.  Lines per block W: x-lines fill at least 256 threads; columns take 2
-// (complex64) or 1 (complex128) adjacent columns (80 contiguous bytes per row)
-// unless the lines are short.
+// Launchers.  Every pass runs 320 threads per block: W = 64 / TL lines (x-lines or
+// adjacent columns), the same geometry as the batched ensemble kernel, so a grid
+// gives bitwise the same result alone or inside an ensemble.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 struct Geo {
-  static constexpr int E = 8;
+  static constexpr int E = (N % 3 == 0) ? 12 : 8;
   static constexpr int TL = N / E;
-  static constexpr int WX = (5 * TL >= 256) ? 1 : (256 + 5 * TL - 1) / (5 * TL);
-  static constexpr int WC = (5 * TL >= 256) ? (sizeof(T) == 4 ? 2 : 1) : (256 + 5 * TL - 1) / (5 * TL);
+  static constexpr int WX = 64 / TL;
+  static constexpr int WC = 64 / TL;
 };
 
 int lines_per_block(int n, bool xline, int esize) {
-  const int TL = n / 8;
-  if (5 * TL >= 256) return xline ? 1 : (esize == 4 ? 2 : 1);
-  return (256 + 5 * TL - 1) / (5 * TL);
+  (void)xline;
+  (void)esize;
+  return 64 / (n / ((n % 3 == 0) ? 12 : 8));
 }
 
 template <typename T, int N, int KIND>
@@ -569,6 +617,7 @@ hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, hipStream_
     case 64: return pass_kind<T, 64>(kind, p, a, st);
     case 128: return pass_kind<T, 128>(kind, p, a, st);
     case 256: return pass_kind<T, 256>(kind, p, a, st);
+    case 384: return pass_kind<T, 384>(kind, p, a, st);
     case 512: return pass_kind<T, 512>(kind, p, a, st);
     default: return hipErrorInvalidValue;
   }
@@ -603,6 +652,7 @@ hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, doubl
     case 64: return obs_kind<T, 64>(kind, p, a, part, st);
     case 128: return obs_kind<T, 128>(kind, p, a, part, st);
     case 256: return obs_kind<T, 256>(kind, p, a, part, st);
+    case 384: return obs_kind<T, 384>(kind, p, a, part, st);
     case 512: return obs_kind<T, 512>(kind, p, a, part, st);
     default: return hipErrorInvalidValue;
   }
@@ -621,6 +671,25 @@ hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_pass_batched(int kind, const void* items, const void* args, long nitems, hipStream_t st) {
+  const int2* it = (const int2*)items;
+  const PassArgs* ar = (const PassArgs*)args;
+  dim3 g((unsigned)nitems), b(320);
+  switch (kind) {
+    case X_FIRST: hipLaunchKernelGGL((k_pass_batched<T, X_FIRST>), g, b, 0, st, it, ar); break;
+    case X_MID: hipLaunchKernelGGL((k_pass_batched<T, X_MID>), g, b, 0, st, it, ar); break;
+    case X_LAST: hipLaunchKernelGGL((k_pass_batched<T, X_LAST>), g, b, 0, st, it, ar); break;
+    case C_PROP: hipLaunchKernelGGL((k_pass_batched<T, C_PROP>), g, b, 0, st, it, ar); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int batched_lines_per_block(int n) { return lines_per_block(n, true, 4); }
+
+template hipError_t launch_pass_batched<float>(int, const void*, const void*, long, hipStream_t);
+template hipError_t launch_pass_batched<double>(int, const void*, const void*, long, hipStream_t);
 template hipError_t launch_pass<float>(int, void*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_pass<double>(int, void*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_obs<float>(int, const void*, const PassArgs&, int, double*, hipStream_t);

@@ -48,6 +48,9 @@ struct PassArgs {
   double s_arg;          // clock value passed by the host (CLOCK_ARG; then written to *clock)
   int clock_mode;
   int advance_clock;
+  // batched passes
+  void* state;           // the instance's state
+  int n_line;            // length of the pass's lines
   // adjoint support
   void* store;           // forward: where to write the pointwise-stage input (or null)
   const void* fwd;       // adjoint: the stored pointwise-stage input of the forward pass
@@ -63,5 +66,9 @@ hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, 
                                int dim, double Omega, double gamma, double d, hipStream_t st);
 // lines per block of the pass kernels (x-lines or columns) for line length n
 int lines_per_block(int n, bool xline, int esize);
+// batched passes: items = int2 (instance, tile), args = PassArgs per instance
+template <typename T>
+hipError_t launch_pass_batched(int kind, const void* items, const void* args, long nitems, hipStream_t st);
+int batched_lines_per_block(int n);
 
 }  // namespace sgp

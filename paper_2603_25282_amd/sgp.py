@@ -20,6 +20,7 @@ SGP_OK = 0
 SGP_C64, SGP_C128 = 0, 1
 SGP_TS2, SGP_TS4 = 2, 4
 SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
+SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
 
 
 class SgpError(RuntimeError):
@@ -73,7 +74,10 @@ def exported_symbols():
     """Names of the C-ABI entry points this binding expects (all declared in sgp.h)."""
     return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
-            "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients"]
+            "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
+            "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
+            "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
+            "sgp_ensemble_last_error"]
 
 
 def _check(rc, ctx=None):
@@ -202,6 +206,81 @@ class Solver:
         if getattr(self, "_ctx", None):
             lib().sgp_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Many 2D grids advanced together (C ABI sgp_ensemble_*): each pass type of a
+    step is one batched launch over every instance's tiles.
+
+    shapes: list of (N, N); Ls: list of half-widths; params_list: list of
+    (c0, c1, c2, Omega, gamma, gx, gy, gz)."""
+
+    def __init__(self, shapes, Ls, params_list, dtype="complex64", device="cuda:0", stream=None):
+        import torch
+        L = lib()
+        vp = ctypes.c_void_p
+        L.sgp_ensemble_create.argtypes = [ctypes.c_int, ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int,
+                                          vp, ctypes.POINTER(vp)]
+        L.sgp_ensemble_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.sgp_ensemble_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+        L.sgp_ensemble_build_propagator.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+        L.sgp_ensemble_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_long]
+        L.sgp_ensemble_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_long]
+        L.sgp_ensemble_destroy.argtypes = [vp]
+        L.sgp_ensemble_destroy.restype = None
+        L.sgp_ensemble_last_error.argtypes = [vp]
+        L.sgp_ensemble_last_error.restype = ctypes.c_char_p
+        n = len(shapes)
+        grids = (_Grid * n)()
+        pars = (_Params * n)()
+        for i, (sh, Li, pr) in enumerate(zip(shapes, Ls, params_list)):
+            grids[i].dim = 2
+            grids[i].n[0], grids[i].n[1], grids[i].n[2] = sh[1], sh[0], 1
+            grids[i].L[0] = grids[i].L[1] = float(Li)
+            pars[i] = _Params(*[float(x) for x in pr])
+        self.shapes = [tuple(sh) for sh in shapes]
+        self.torch_dtype = {"complex64": torch.complex64, "complex128": torch.complex128}[dtype]
+        code = SGP_C64 if dtype == "complex64" else SGP_C128
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            sp = _stream_ptr(stream)
+        h = vp()
+        rc = L.sgp_ensemble_create(n, grids, pars, code, sp, ctypes.byref(h))
+        if rc != SGP_OK:
+            raise SgpError(f"sgp_ensemble_create {rc}: {L.sgp_ensemble_last_error(None).decode()}")
+        self._h = h
+        nb = ctypes.c_size_t()
+        self._chk(L.sgp_ensemble_workspace_size(h, ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self._chk(L.sgp_ensemble_set_workspace(h, vp(self.workspace.data_ptr()), nb.value))
+
+    def _chk(self, rc):
+        if rc != SGP_OK:
+            raise SgpError(f"sgp ensemble error {rc}: {lib().sgp_ensemble_last_error(self._h).decode()}")
+
+    def build_propagator(self, tau, scheme):
+        self._chk(lib().sgp_ensemble_build_propagator(self._h, float(tau), int(scheme)))
+
+    def step(self, psis, nsteps):
+        for p, sh in zip(psis, self.shapes):
+            if p.dtype != self.torch_dtype or tuple(p.shape) != sh + (5,) or not p.is_contiguous():
+                raise SgpError("ensemble states must be contiguous (N, N, 5) tensors of the ensemble dtype")
+        arr = (ctypes.c_void_p * len(psis))(*[p.data_ptr() for p in psis])
+        self._chk(lib().sgp_ensemble_step(self._h, arr, int(nsteps)))
+
+    def set_option(self, option, value):
+        self._chk(lib().sgp_ensemble_set_option(self._h, int(option), int(value)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sgp_ensemble_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:
