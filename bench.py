@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the fwd+adjoint measurement (0 to skip)")
     ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the measurements, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -158,6 +160,12 @@ def main():
         out["cpu_baseline"] = {"value": npts * k / tc, "unit": "gp-steps/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
                                "sample": f"{k} TS4 steps of the same workload (FP64, own FFT) in {tc:.1f} s"}
+    if a.calib_copy_mb > 0:
+        src = torch.empty(a.calib_copy_mb * 2 ** 20, dtype=torch.uint8, device=s.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel()
     print(json.dumps(out), flush=True)
 
 

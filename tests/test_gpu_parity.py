@@ -162,3 +162,19 @@ def test_3d_observables(dtype):
     tol = 1e-12 if dtype == "complex128" else 2e-6
     scale = np.array([1.0, abs(ref[1]) + 1.0, 1.0, 1.0])
     assert np.all(np.abs(got - ref) <= tol * scale)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_config3_full_200_steps(dtype):
+    # Full 3D workload: 128^3 TS4, 200 steps, against the oracle's stored samples.
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3_reference.npz"))
+    cfg = I.C3
+    psi0 = I.initial_state(cfg)
+    got, s = run_gpu(cfg.shape, cfg.L, cfg.params, psi0, cfg.order, cfg.tau, cfg.steps, dtype=dtype)
+    err = rel_l2(got.reshape(5, -1)[:, ref["idx"]], ref["samples"])
+    from tests.gpu_util import to_gpu
+    obs = s.observables(to_gpu(s, got))
+    print(f"3D 200-step rel l2 (samples) {err:.3e}; gpu obs {obs}; oracle obs {ref['obs']}")
+    assert err <= TOL[dtype]
+    assert abs(obs[0] - ref["obs"][0]) <= (1e-11 if dtype == "complex128" else 1e-5)
