@@ -461,10 +461,10 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
   const double phi = K.d * (V + K.c0p * (double)rho);
   const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
   const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
-  double sd, cd, sh, chh;
-  sincos(red, &sd, &cd);
+  double sh, chh;
   sincos(0.5 * red, &sh, &chh);
-  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-sd));
+  // exp(-i phi) - 1 = -2 sin^2(phi/2) - i sin(phi), sin(phi) = 2 sin(phi/2) cos(phi/2)
+  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-2.0 * sh * chh));
   sym4_apply_inc<T>(as, beta, phs, b);
 #pragma unroll
   for (int i = 0; i < 5; ++i) p[i] = b[i];
@@ -531,10 +531,9 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
   const double phi = K.d * (V + K.c0p * (double)rho);
   const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
   const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
-  double sd, cd, sh, chh;
-  sincos(red, &sd, &cd);
+  double sh, chh;
   sincos(0.5 * red, &sh, &chh);
-  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-sd));
+  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-2.0 * sh * chh));
   // psi' and h = exp(i phi) R^H g'
   cx<T> out[5], h[5];
 #pragma unroll

@@ -24,7 +24,14 @@
 
 namespace sgp {
 
-template <int N> struct PadLine { static constexpr int size = LdsLine<N>::size; };
+// LDS line stride of the FFT exchanges: N + N/8 (one pad slot per 8) plus a per-length
+// extra that spreads the 5 component lines of adjacent lanes over the 32 banks
+// (chosen with a bank-conflict model of every exchange pattern).
+template <int N> struct PadLine {
+  static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 3 : N == 64 ? 5 : N == 384 ? 25
+                             : N == 32 ? 1 : N == 16 ? 9 : 1;
+  static constexpr int size = N + N / 8 + extra;
+};
 
 // Block index -> logical tile index so that the 8 XCDs (which take blocks round
 // robin) each process one contiguous range of tiles and share their L2 lines.
@@ -33,9 +40,16 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks) {
   return (b % 8) * (nblocks / 8) + b / 8;
 }
 
+// Trap rotation cos/sin(Omega s): from the host value (first pass of a call) or from
+// the device clock, whose slots 1, 2 hold cos and sin of the current angle (written by
+// whichever pass last moved the clock).
 __device__ __forceinline__ void trap_angle(const PassArgs& a, double& c, double& s) {
-  const double clk = a.clock_mode == CLOCK_ARG ? a.s_arg : a.clock[0];
-  sincos(a.Omega * clk, &s, &c);
+  if (a.clock_mode == CLOCK_ARG) {
+    sincos(a.Omega * a.s_arg, &s, &c);
+  } else {
+    c = a.clock[1];
+    s = a.clock[2];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,10 +311,23 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
     for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
   }
   if constexpr (XL && !ADJ) {
-    if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) a.clock[0] = a.s_arg;
+    if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) {
+      a.clock[0] = a.s_arg;
+      double sn, cn;
+      sincos(a.Omega * a.s_arg, &sn, &cn);
+      a.clock[1] = cn;
+      a.clock[2] = sn;
+    }
   }
   if constexpr (KIND == C_PROP) {
-    if (a.advance_clock && tile == 0 && tid == 0) a.clock[0] += a.d;
+    if (a.advance_clock && tile == 0 && tid == 0) {
+      const double s1 = a.clock[0] + a.d;
+      double sn, cn;
+      sincos(a.Omega * s1, &sn, &cn);
+      a.clock[0] = s1;
+      a.clock[1] = cn;
+      a.clock[2] = sn;
+    }
   }
 }
 
