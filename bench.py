@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the fwd+adjoint measurement (0 to skip)")
     ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
+    ap.add_argument("--plan", default="auto",
+                    help='register plans: "auto" (autotuned before the timed region), "default", or widths "ex,ey[,ez]"')
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the measurements, run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -60,6 +62,11 @@ def main():
     s = Solver(cfg.shape, cfg.L, cfg.params, dtype=a.dtype)
     s.build_propagator(cfg.tau, cfg.order)
     psi = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).contiguous()
+    if a.plan == "auto":
+        s.autotune(psi, cfg.order, steps=20)
+    elif a.plan != "default":
+        s.set_plan([int(x) for x in a.plan.split(",")])
+    plan = s.get_plan()
 
     # warmup (also captures the step graph)
     s.step(psi, a.warmup)
@@ -116,7 +123,7 @@ def main():
         "dtype": "f32" if a.dtype == "complex64" else "f64",
         "data": "synthetic (seeded Gaussian + noise initial state)",
         "config": {"workload": cfg.name, "grid": list(cfg.shape), "L": cfg.L, "scheme": f"TS{cfg.order}",
-                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "finite": finite},
+                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "plan": plan, "finite": finite},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,
@@ -137,7 +144,7 @@ def main():
         gdir = torch.randn(p0.shape, dtype=s.torch_dtype, device=s.device)
 
         def fwd_bwd():
-            out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, n_adj, order=cfg.order, K=a.K)
+            out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, n_adj, order=cfg.order, K=a.K, plan=plan)
             J = torch.sum((torch.conj(gdir) * out).real)
             J.backward()
 

@@ -18,18 +18,22 @@ from .sgp import Solver
 PARAM_ORDER = ("gamma", "Omega", "c0", "c1", "c2")
 
 
-def _solver(shape, L, params, trap, dtype, tau, order):
+def _solver(shape, L, params, trap, dtype, tau, order, plan=None, psi=None):
     g, Om, c0, c1, c2 = [float(x) for x in params]
     s = Solver(shape, L, (c0, c1, c2, Om, g, trap[0], trap[1], trap[2]), dtype=dtype)
     s.build_propagator(tau, order)
+    if plan == "auto":
+        s.autotune(psi, order)
+    elif plan is not None:
+        s.set_plan(plan)
     return s
 
 
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, psi0, params, shape, L, trap, tau, nsteps, order, K, t0):
+    def forward(ctx, psi0, params, shape, L, trap, tau, nsteps, order, K, t0, plan):
         dtype = "complex64" if psi0.dtype == torch.complex64 else "complex128"
-        s = _solver(shape, L, params.detach().cpu().tolist(), trap, dtype, tau, order)
+        s = _solver(shape, L, params.detach().cpu().tolist(), trap, dtype, tau, order, plan, psi0.detach())
         psi = psi0.detach().clone().contiguous()
         ckpts = []
         for n0 in range(0, nsteps, K):
@@ -59,11 +63,14 @@ class _Evolve(torch.autograd.Function):
             s.time = t0 + n0 * tau
             s.adjoint_segment(lam, ns, store)
         dpar = torch.tensor(s.adjoint_gradients(reset=True), dtype=torch.float64)
-        return lam, dpar, None, None, None, None, None, None, None, None
+        return lam, dpar, None, None, None, None, None, None, None, None, None
 
 
-def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0):
+def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0, plan=None):
+    """plan: None (default register plans), a list of plan widths per axis (x, y (, z)),
+    or "auto" (autotuned, through the JSON plan cache)."""
     if not isinstance(params, torch.Tensor):
         params = torch.tensor(params, dtype=torch.float64)
+    plan = plan if plan is None or plan == "auto" else tuple(int(e) for e in plan)
     return _Evolve.apply(psi0, params, tuple(shape), L, tuple(trap), float(tau), int(nsteps), int(order), int(K),
-                         float(t0))
+                         float(t0), plan)

@@ -31,17 +31,23 @@ std::vector<int> plan_of(bool fwd) {
 
 bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 384 || n == 512; }
 
-std::vector<int> plan_radices(int n, bool fwd) {
-  switch (n) {
-    case 16: return plan_of<16, 8>(fwd);
-    case 32: return plan_of<32, 8>(fwd);
-    case 64: return plan_of<64, 8>(fwd);
-    case 128: return plan_of<128, 8>(fwd);
-    case 256: return plan_of<256, 8>(fwd);
-    case 384: return plan_of<384, 12>(fwd);
-    case 512: return plan_of<512, 8>(fwd);
-    default: return {};
-  }
+std::vector<int> plan_radices(int n, int e, bool fwd) {
+#define SGP_PLAN(NN, EE) \
+  if (n == NN && e == EE) return plan_of<NN, EE>(fwd);
+  SGP_PLAN(16, 4) SGP_PLAN(32, 4) SGP_PLAN(64, 4) SGP_PLAN(128, 4) SGP_PLAN(256, 4) SGP_PLAN(512, 4)
+  SGP_PLAN(16, 8) SGP_PLAN(32, 8) SGP_PLAN(64, 8) SGP_PLAN(128, 8) SGP_PLAN(256, 8) SGP_PLAN(512, 8)
+  SGP_PLAN(64, 16) SGP_PLAN(128, 16) SGP_PLAN(256, 16) SGP_PLAN(512, 16)
+  SGP_PLAN(384, 12) SGP_PLAN(384, 24)
+#undef SGP_PLAN
+  return {};
+}
+
+// Plan widths compiled for line length n (the default first).
+std::vector<int> plan_widths(int n) {
+  std::vector<int> out{default_elems(n)};
+  for (int e : kPlanElems)
+    if (e != default_elems(n) && plan_ok(n, e)) out.push_back(e);
+  return out;
 }
 
 // Twiddle table of a plan: for each pass with NS > 1, for k in [0, NS), the values
@@ -81,6 +87,9 @@ struct sgp_ctx {
   size_t off_gacc;
   long ngacc = 0;  // blocks with a gradient slot
 
+  // register plan width E of the passes along each axis
+  int plan_e[3] = {0, 0, 0};
+
   int scheme = 0;
   double tau = 0.0;
   int nprop = 0;
@@ -97,6 +106,7 @@ struct sgp_ctx {
   bool use_graph = true;
 
   long npts() const { return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1); }
+  int elems(int axis) const { return plan_e[axis]; }
   void* at(size_t off) const { return ws + off; }
 };
 
@@ -131,7 +141,7 @@ template <typename T>
 hipError_t upload_twiddles(sgp_ctx* c) {
   for (int ax = 0; ax < c->g.dim; ++ax) {
     for (int dir = 0; dir < 2; ++dir) {
-      auto tab = twiddle_table(plan_radices(c->g.n[ax], dir == 0));
+      auto tab = twiddle_table(plan_radices(c->g.n[ax], c->elems(ax), dir == 0));
       // each twiddle as a (hi, lo) pair: hi = w rounded to T, lo = (w - hi) rounded
       std::vector<T> buf(4 * tab.size() + 4);
       for (size_t i = 0; i < tab.size(); ++i) {
@@ -209,7 +219,7 @@ hipError_t run_xpass(sgp_ctx* c, hipStream_t st, int mode, void* psi, double d, 
   a.d = d;
   a.s_arg = s_arg;
   a.clock_mode = clock_mode;
-  return launch_pass<T>(mode, psi, a, c->g.n[0], st);
+  return launch_pass<T>(mode, psi, a, c->g.n[0], c->elems(0), st);
 }
 
 template <typename T>
@@ -222,7 +232,7 @@ hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi
   a.kin_l = c->at(c->off_kin[table][axis]);
   a.d = d;
   a.advance_clock = (mode == C_PROP) ? 1 : 0;
-  return launch_pass<T>(mode, psi, a, c->g.n[axis], st);
+  return launch_pass<T>(mode, psi, a, c->g.n[axis], c->elems(axis), st);
 }
 
 // Store-mode and adjoint variants of the passes.
@@ -238,7 +248,7 @@ hipError_t run_xpass_ex(sgp_ctx* c, int kind, void* psi, double d, int clock_mod
   a.store = store;
   a.fwd = fwd;
   a.gacc = (double*)c->at(c->off_gacc);
-  return launch_pass<T>(kind, psi, a, c->g.n[0], c->st);
+  return launch_pass<T>(kind, psi, a, c->g.n[0], c->elems(0), c->st);
 }
 
 template <typename T>
@@ -255,7 +265,7 @@ hipError_t run_colpass_ex(sgp_ctx* c, int kind, int axis, void* psi, int table, 
   a.store = store;
   a.fwd = fwd;
   a.gacc = (double*)c->at(c->off_gacc);
-  return launch_pass<T>(kind, psi, a, c->g.n[axis], c->st);
+  return launch_pass<T>(kind, psi, a, c->g.n[axis], c->elems(axis), c->st);
 }
 
 // One exact linear substep on x-transformed data: 2D Y-pass, 3D Y1 + Z + Y2.
@@ -408,11 +418,89 @@ int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   return SGP_OK;
 }
 
+// Register plan of the passes along one axis; the twiddle tables follow the plan.
+template <typename T>
+int set_plan_impl(sgp_ctx* c, int axis, int e) {
+  if (axis < 0 || axis >= c->g.dim) return fail(c, SGP_ERR_ARG, "axis out of range");
+  if (e == 0) e = default_elems(c->g.n[axis]);
+  if (!plan_ok(c->g.n[axis], e))
+    return fail(c, SGP_ERR_ARG, "plan width " + std::to_string(e) + " not available for length " +
+                                    std::to_string(c->g.n[axis]));
+  if (c->plan_e[axis] == e) return SGP_OK;
+  c->plan_e[axis] = e;
+  drop_graph(c);
+  if (c->ws) {
+    hipError_t r = upload_twiddles<T>(c);
+    if (r != hipSuccess) return hip_fail(c, r, "twiddle upload");
+  }
+  return SGP_OK;
+}
+
+// Autotuner: per axis in turn (the other axes at their current best), time `steps`
+// whole steps (the sgp_step path, graphs included) with every plan width of that
+// axis and keep the fastest.  psi is advanced by the timed steps; the context time
+// is restored.
+template <typename T>
+int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_ms) {
+  const double t_save = c->t;
+  hipEvent_t e0, e1;
+  hipError_t r = hipEventCreate(&e0);
+  if (r != hipSuccess) return hip_fail(c, r, "event create");
+  r = hipEventCreate(&e1);
+  if (r != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, r, "event create"); }
+  auto time_steps = [&](double* ms) -> int {
+    int rc = step_impl<T>(c, psi, steps);  // untimed: graph capture, warm caches
+    if (rc != SGP_OK) return rc;
+    hipError_t q = hipEventRecord(e0, c->st);
+    if (q != hipSuccess) return hip_fail(c, q, "event record");
+    rc = step_impl<T>(c, psi, steps);
+    if (rc != SGP_OK) return rc;
+    q = hipEventRecord(e1, c->st);
+    if (q == hipSuccess) q = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (q == hipSuccess) q = hipEventElapsedTime(&f, e0, e1);
+    if (q != hipSuccess) return hip_fail(c, q, "autotune timing");
+    *ms = (double)f / steps;
+    return SGP_OK;
+  };
+  double best = 0.0;
+  int rc = time_steps(&best);
+  for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) {
+    const int start = c->plan_e[ax];
+    int best_e = start;
+    for (int e : plan_widths(c->g.n[ax])) {
+      if (e == start) continue;
+      double ms = 0.0;
+      rc = set_plan_impl<T>(c, ax, e);
+      if (rc == SGP_OK) rc = time_steps(&ms);
+      if (rc != SGP_OK) break;
+      if (ms < best) { best = ms; best_e = e; }
+    }
+    if (rc == SGP_OK) rc = set_plan_impl<T>(c, ax, best_e);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->t = t_save;
+  if (rc != SGP_OK) return rc;
+  for (int ax = 0; ax < 3; ++ax) out_e[ax] = ax < c->g.dim ? c->plan_e[ax] : 0;
+  if (best_ms) *best_ms = best;
+  return SGP_OK;
+}
+
 // Observables: one x-line pass (d_x, pointwise terms) and one column pass per other
 // axis; FP64 block partials summed on the host in block order (deterministic).
-long obs_nblocks(const sgp_ctx* c, int axis) {
+long obs_nblocks(const sgp_ctx* c, int axis, int e) {
   const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
-  const int W = lines_per_block(c->g.n[axis], axis == 0, (int)c->esize);
+  const int W = obs_lines_per_block(c->g.n[axis], e);
+  if (axis == 0) return ((long)ny * nz + W - 1) / W;
+  const long nouter = axis == 1 ? nz : ny;
+  return ((nx + W - 1) / W) * nouter;
+}
+
+// Blocks of a pass kernel along `axis` with plan width e (one adjoint slot each).
+long pass_nblocks(const sgp_ctx* c, int axis, int e) {
+  const int nx = c->g.n[0], ny = c->g.n[1], nz = c->g.dim == 3 ? c->g.n[2] : 1;
+  const int W = lines_per_block(c->g.n[axis], e);
   if (axis == 0) return ((long)ny * nz + W - 1) / W;
   const long nouter = axis == 1 ? nz : ny;
   return ((nx + W - 1) / W) * nouter;
@@ -433,9 +521,9 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
     }
     a.s_arg = c->t;
     const int kind = axis == 0 ? OBS_X : (axis == 1 ? OBS_Y : OBS_Z);
-    hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], part, c->st);
+    hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], c->elems(axis), part, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "observables launch");
-    const long nb = obs_nblocks(c, axis);
+    const long nb = obs_nblocks(c, axis, c->elems(axis));
     std::vector<double> host((size_t)nb * NOBS);
     e = hipMemcpyAsync(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -534,7 +622,7 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   for (int i = 0; i < grid->dim; ++i) {
     if (!supported_n(grid->n[i]))
       return fail(nullptr, SGP_ERR_ARG, "unsupported grid size " + std::to_string(grid->n[i]) +
-                                            " (supported: 16, 32, 64, 128, 256, 512)");
+                                            " (supported: 16, 32, 64, 128, 256, 384, 512)");
     if (!(grid->L[i] > 0.0) || !std::isfinite(grid->L[i])) return fail(nullptr, SGP_ERR_ARG, "L must be > 0");
   }
   const double* pv = &params->c0;
@@ -549,12 +637,18 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   c->dtype = dtype;
   c->st = (hipStream_t)hip_stream;
   c->esize = dtype == SGP_C64 ? 4 : 8;
+  for (int ax = 0; ax < c->g.dim; ++ax) c->plan_e[ax] = default_elems(c->g.n[ax]);
   // workspace layout
   size_t off = 0;
   for (int ax = 0; ax < 3; ++ax)
     for (int dir = 0; dir < 2; ++dir) {
       c->off_tw[ax][dir] = off;
-      if (ax < c->g.dim) off += align256(4 * c->esize * (twiddle_table(plan_radices(c->g.n[ax], dir == 0)).size() + 1));
+      // room for the largest table over the plans of this axis (plans can change later)
+      size_t most = 0;
+      if (ax < c->g.dim)
+        for (int e : plan_widths(c->g.n[ax]))
+          most = std::max(most, twiddle_table(plan_radices(c->g.n[ax], e, dir == 0)).size());
+      if (ax < c->g.dim) off += align256(4 * c->esize * (most + 1));
     }
   const size_t nxy = (size_t)c->g.n[0] * c->g.n[1];
   for (int k = 0; k < 2; ++k) {
@@ -568,12 +662,14 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   c->off_clock = off;
   off += 256;
   c->off_part = off;
+  // block partials and adjoint parameter slots: one per block of the largest pass
+  // over every plan
   long maxb = 0;
-  for (int axis = 0; axis < c->g.dim; ++axis) maxb = std::max(maxb, obs_nblocks(c, axis));
+  for (int axis = 0; axis < c->g.dim; ++axis)
+    for (int e : plan_widths(c->g.n[axis]))
+      maxb = std::max(maxb, std::max(obs_nblocks(c, axis, e), pass_nblocks(c, axis, e)));
   off += align256(sizeof(double) * NOBS * maxb);
-  // adjoint parameter slots: one per block of the largest pass
-  long gb = 0;
-  for (int axis = 0; axis < c->g.dim; ++axis) gb = std::max(gb, obs_nblocks(c, axis));
+  const long gb = maxb;
   c->ngacc = gb;
   c->off_gacc = off;
   off += align256(sizeof(double) * NGRAD * gb);
@@ -725,6 +821,33 @@ int sgp_adjoint_gradients(sgp_ctx* c, double out[5], int reset) {
     if (e != hipSuccess) return hip_fail(c, e, "gradient reset");
   }
   return SGP_OK;
+}
+
+int sgp_plan_widths(int n, int* out, int max_out) {
+  if (!supported_n(n) || (max_out > 0 && !out)) return SGP_ERR_ARG;
+  std::vector<int> w = plan_widths(n);
+  for (int i = 0; i < (int)w.size() && i < max_out; ++i) out[i] = w[i];
+  return (int)w.size();
+}
+
+int sgp_set_plan(sgp_ctx* c, int axis, int elems) {
+  if (!c) return SGP_ERR_ARG;
+  return c->dtype == SGP_C64 ? set_plan_impl<float>(c, axis, elems) : set_plan_impl<double>(c, axis, elems);
+}
+
+int sgp_get_plan(const sgp_ctx* c, int axis, int* elems) {
+  if (!c || !elems || axis < 0 || axis >= c->g.dim) return SGP_ERR_ARG;
+  *elems = c->plan_e[axis];
+  return SGP_OK;
+}
+
+int sgp_autotune(sgp_ctx* c, void* psi, int steps, int elems_out[3], double* ms_per_step) {
+  if (!c || !psi || !elems_out) return fail(c, SGP_ERR_ARG, "null argument");
+  if (steps < 1) return fail(c, SGP_ERR_ARG, "steps must be >= 1");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  return c->dtype == SGP_C64 ? autotune_impl<float>(c, psi, steps, elems_out, ms_per_step)
+                             : autotune_impl<double>(c, psi, steps, elems_out, ms_per_step);
 }
 
 int sgp_set_option(sgp_ctx* c, int option, long value) {

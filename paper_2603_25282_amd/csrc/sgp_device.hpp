@@ -247,18 +247,28 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre,
 // reverse order so that the two share the register layout at both ends.
 template <int... Rs> struct RadixList {};
 template <int N, int E> struct Plan;
+// E = 8 (defaults for powers of two)
 template <> struct Plan<16, 8> { using fwd = RadixList<2, 8>; using inv = RadixList<8, 2>; };
 template <> struct Plan<32, 8> { using fwd = RadixList<4, 8>; using inv = RadixList<8, 4>; };
 template <> struct Plan<64, 8> { using fwd = RadixList<8, 8>; using inv = RadixList<8, 8>; };
 template <> struct Plan<128, 8> { using fwd = RadixList<2, 8, 8>; using inv = RadixList<8, 8, 2>; };
 template <> struct Plan<256, 8> { using fwd = RadixList<4, 8, 8>; using inv = RadixList<8, 8, 4>; };
 template <> struct Plan<512, 8> { using fwd = RadixList<8, 8, 8>; using inv = RadixList<8, 8, 8>; };
-template <> struct Plan<1024, 8> { using fwd = RadixList<2, 8, 8, 8>; using inv = RadixList<8, 8, 8, 2>; };
-template <> struct Plan<48, 12> { using fwd = RadixList<3, 4, 4>; using inv = RadixList<4, 4, 3>; };
-template <> struct Plan<96, 12> { using fwd = RadixList<3, 4, 4, 2>; using inv = RadixList<2, 4, 4, 3>; };
-template <> struct Plan<192, 12> { using fwd = RadixList<3, 4, 4, 4>; using inv = RadixList<4, 4, 4, 3>; };
+// E = 4: radix 2 and 4 only, twice the threads per line
+template <> struct Plan<16, 4> { using fwd = RadixList<4, 4>; using inv = RadixList<4, 4>; };
+template <> struct Plan<32, 4> { using fwd = RadixList<2, 4, 4>; using inv = RadixList<4, 4, 2>; };
+template <> struct Plan<64, 4> { using fwd = RadixList<4, 4, 4>; using inv = RadixList<4, 4, 4>; };
+template <> struct Plan<128, 4> { using fwd = RadixList<2, 4, 4, 4>; using inv = RadixList<4, 4, 4, 2>; };
+template <> struct Plan<256, 4> { using fwd = RadixList<4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4>; };
+template <> struct Plan<512, 4> { using fwd = RadixList<2, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 2>; };
+// E = 16: the E = 8 radices, two butterflies per thread and pass
+template <> struct Plan<64, 16> { using fwd = RadixList<8, 8>; using inv = RadixList<8, 8>; };
+template <> struct Plan<128, 16> { using fwd = RadixList<2, 8, 8>; using inv = RadixList<8, 8, 2>; };
+template <> struct Plan<256, 16> { using fwd = RadixList<4, 8, 8>; using inv = RadixList<8, 8, 4>; };
+template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = RadixList<8, 8, 8>; };
+// 384 = 3 * 2^7: E = 12 (default) and E = 24
 template <> struct Plan<384, 12> { using fwd = RadixList<3, 4, 4, 4, 2>; using inv = RadixList<2, 4, 4, 4, 3>; };
-template <> struct Plan<768, 12> { using fwd = RadixList<3, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 3>; };
+template <> struct Plan<384, 24> { using fwd = RadixList<3, 8, 8, 2>; using inv = RadixList<2, 8, 8, 3>; };
 
 template <typename T, int N, int E, int SIGN, int NS, int NC, int NBUF, int SYNC, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,

@@ -57,18 +57,43 @@ struct PassArgs {
   double* gacc;          // adjoint: per-block parameter slots [block][NGRAD], accumulated
 };
 
+// Register plans of the FFT line kernels: E elements per thread of a line of
+// length N (the radix sequence follows from N and E, see Plan<N, E>).  E = 8 for
+// powers of two and 12 for 384 are the defaults; the others are autotuning
+// alternatives (E = 4: twice the threads, E = 16 / 24: more registers per thread).
+constexpr bool plan_ok(int n, int e) {
+  return (n == 384) ? (e == 12 || e == 24)
+                    : ((n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512) &&
+                       (e == 4 || e == 8 || (e == 16 && n >= 64)));
+}
+constexpr int default_elems(int n) { return n % 3 == 0 ? 12 : 8; }
+constexpr int kPlanElems[] = {4, 8, 12, 16, 24};
+// lines per block of the pass kernels for line length n with plan width e
+constexpr int lines_per_block(int n, int e) { return n / e >= 64 ? 1 : 64 / (n / e); }
+// lines per block of the observables kernels (their LDS tile holds psi and its
+// derivative: at most 512 points per block)
+constexpr int obs_lines_per_block(int n, int e) {
+  int w = lines_per_block(n, e);
+  while (w > 1 && w * n > 512) w /= 2;
+  return w;
+}
+
 template <typename T>
-hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, hipStream_t st);
+hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st);
 template <typename T>
-hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, double* part, hipStream_t st);
+hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e, double* part, hipStream_t st);
 template <typename T>
 hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, const int* n, const double* L,
                                int dim, double Omega, double gamma, double d, hipStream_t st);
-// lines per block of the pass kernels (x-lines or columns) for line length n
-int lines_per_block(int n, bool xline, int esize);
-// batched passes: items = int2 (instance, tile), args = PassArgs per instance
+// batched passes (default plans): items = int2 (instance, tile), args = PassArgs per instance
 template <typename T>
 hipError_t launch_pass_batched(int kind, const void* items, const void* args, long nitems, hipStream_t st);
 int batched_lines_per_block(int n);
+
+// per-plan-width launchers, each (T, E) compiled in its own translation unit
+template <typename T, int E>
+hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st);
+template <typename T, int E>
+hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, double* part, hipStream_t st);
 
 }  // namespace sgp

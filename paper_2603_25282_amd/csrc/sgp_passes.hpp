@@ -1,0 +1,680 @@
+// Split-step kernels for the rotating SOC spin-2 GPE on gfx950.
+//
+// State layout: [nz][ny][nx][5] complex (components innermost).
+//
+// One linear substep of the compact splitting (Sec. 3.1) in 2D is two passes over
+// the state; each pass reads and writes every value once:
+//   X-pass (lines along x): inverse FFT along x, exact nonlinear flow per point
+//                           (Sec. 3.2) with the trap at R(Omega s) x, forward FFT.
+//   Y-pass (lines along y): forward FFT along y, exact linear propagator per
+//                           wavevector (eq. sl1), inverse FFT along y.
+// Between passes the state is held x-transformed (Fourier in x, physical in y).
+// The first X-pass of a call starts from physical data (no inverse FFT) and the
+// last one ends in physical data (no forward FFT).  3D: Y1 (forward y),
+// Z (forward z, propagator, inverse z), Y2 (inverse y).
+//
+// Work split inside a block: W lines x 5 components; each (line, component) is
+// transformed by TL = N/E threads holding E elements each (register Stockham FFT
+// with LDS exchanges).  The pointwise stage (nonlinear flow or propagator) needs the
+// 5 components of a point together: the block writes its lines into an LDS tile
+// (components innermost), every thread updates whole points from the tile, and
+// the FFT threads read their elements back.
+#pragma once
+#include "sgp_device.hpp"
+#include "sgp_kernels.hpp"
+
+namespace sgp {
+
+// LDS line stride of the FFT exchanges: N + N/8 (one pad slot per 8) plus a per-length
+// extra that spreads the 5 component lines of adjacent lanes over the 32 banks
+// (chosen with a bank-conflict model of every exchange pattern).
+template <int N> struct PadLine {
+  static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 3 : N == 64 ? 5 : N == 384 ? 25
+                             : N == 32 ? 1 : N == 16 ? 9 : 1;
+  static constexpr int size = N + N / 8 + extra;
+};
+
+// Block index -> logical tile index so that the 8 XCDs (which take blocks round
+// robin) each process one contiguous range of tiles and share their L2 lines.
+__device__ __forceinline__ long xcd_tile(long b, long nblocks) {
+  if (nblocks % 8) return b;
+  return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+// Trap rotation cos/sin(Omega s): from the host value (first pass of a call) or from
+// the device clock, whose slots 1, 2 hold cos and sin of the current angle (written by
+// whichever pass last moved the clock).
+__device__ __forceinline__ void trap_angle(const PassArgs& a, double& c, double& s) {
+  if (a.clock_mode == CLOCK_ARG) {
+    sincos(a.Omega * a.s_arg, &s, &c);
+  } else {
+    c = a.clock[1];
+    s = a.clock[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic pass.  KIND selects the line direction and the stages:
+//   X_FIRST: load phys -> NL -> FFTx -> store       X_MID: iFFTx -> NL -> FFTx
+//   X_LAST:  iFFTx -> NL -> store phys              X_NLONLY: NL only
+//   C_PROP:  FFT -> propagator -> iFFT (column)     C_FWD / C_INV: FFT / iFFT only
+// ---------------------------------------------------------------------------
+template <int KIND> struct KindInfo {
+  static constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
+                             KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  static constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+  static constexpr bool ADJ = XADJ || KIND == C_ADJ;
+  static constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
+};
+
+// LDS elements (per re / im array) a pass needs.
+template <int N, int W, int KIND>
+constexpr int pass_lds() {
+  constexpr int TILE = KindInfo<KIND>::PW ? W * N * 5 : 0;
+  constexpr int XCH = W * 5 * PadLine<N>::size;
+  return TILE > XCH ? TILE : XCH;
+}
+
+// Body of one block of a pass over `tile` (W lines), with caller-provided LDS.
+template <typename T, int N, int E, int W, int KIND>
+__device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArgs& a, long tile, T* lre, T* lim,
+                                          double (*gred)[NGRAD]) {
+  constexpr int TL = N / E;
+  constexpr int NT = W * 5 * TL;
+  constexpr int LS = PadLine<N>::size;
+  constexpr bool XL = KindInfo<KIND>::XL;
+  constexpr bool XADJ = KindInfo<KIND>::XADJ;
+  constexpr bool ADJ = KindInfo<KIND>::ADJ;
+  constexpr bool PW = KindInfo<KIND>::PW;
+
+  const int tid = threadIdx.x;
+  const int c = tid % 5;
+  const int rest = tid / 5;
+  // x-lines: the TL threads of a line are adjacent (contiguous loads);
+  // columns: the W columns are adjacent (W*5 contiguous values per row)
+  const int col = XL ? rest / TL : rest % W;
+  const int t = XL ? rest % TL : rest / W;
+
+  // line geometry
+  long base;        // element offset of the line's first point (component 0)
+  long estride;     // element stride between consecutive points of the line
+  long line0 = 0;   // x-lines: first line of the block (line = z * ny + y)
+  long o = 0, kx0 = 0;
+  bool active;
+  if constexpr (XL) {
+    line0 = tile * W;
+    const long line = line0 + col;
+    active = line < a.nlines;
+    base = (active ? line : 0) * (long)N * 5;
+    estride = 5;
+  } else {
+    const long ncolblk = (a.ncols + W - 1) / W;
+    o = tile / ncolblk;
+    kx0 = (tile % ncolblk) * W;
+    const long kx = kx0 + col;
+    active = kx < a.ncols;
+    base = o * a.outer_stride + (active ? kx : 0) * 5;
+    estride = a.stride;
+  }
+
+  cx<T> v[1][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
+
+  T* xre = lre + (col * 5 + c) * LS;
+  T* xim = lim + (col * 5 + c) * LS;
+  const cx<T>* twf = reinterpret_cast<const cx<T>*>(a.tw_fwd);
+  const cx<T>* twi = reinterpret_cast<const cx<T>*>(a.tw_inv);
+
+  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID)
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+
+  // forward store mode: keep the pointwise-stage input for the adjoint
+  if constexpr (PW && !ADJ) {
+    if (a.store != nullptr && active) {
+      cx<T>* st = reinterpret_cast<cx<T>*>(a.store);
+#pragma unroll
+      for (int m = 0; m < E; ++m) st[base + (long)(t + TL * m) * estride + c] = v[0][m];
+    }
+  }
+  double gacc[NGRAD] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  if constexpr (PW) {
+    // to the tile: point (col, j) component c at (col * N + j) * 5 + c
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int o5 = (col * N + t + TL * m) * 5 + c;
+      lre[o5] = v[0][m].re;
+      lim[o5] = v[0][m].im;
+    }
+    __syncthreads();
+    if constexpr (XL) {
+      NLCoef K;
+      K.d = a.d;
+      K.c0p = a.c0p;
+      K.c1 = a.c1;
+      K.c2 = a.c2;
+      double ct, st;
+      trap_angle(a, ct, st);
+      for (int pt = tid; pt < W * N; pt += NT) {
+        const int pc = pt / N, j = pt % N;
+        const long line = line0 + pc;
+        const int iy = (int)(line % a.ny), iz = (int)(line / a.ny);
+        const double x = -a.L[0] + j * a.h[0];
+        const double y = -a.L[1] + iy * a.h[1];
+        const double z = -a.L[2] + iz * a.h[2];
+        const double X = ct * x + st * y, Y = -st * x + ct * y;
+        const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y + a.g2[2] * z * z);
+        cx<T> p[5];
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) p[cc] = mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
+        if constexpr (XADJ) {
+          // forward input of this nonlinear substep at the point, from the store
+          const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + (line < a.nlines ? line : 0) * (long)N * 5 + j * 5;
+          cx<T> q[5];
+#pragma unroll
+          for (int cc = 0; cc < 5; ++cc) q[cc] = fw[cc];
+          // dV/dOmega = s (gx^2 - gy^2) X Y (trap at R(Omega s) x)
+          const double dVdO = a.s_arg * (a.g2[0] - a.g2[1]) * X * Y;
+          double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+          nl_point_adj<T>(q, p, V, dVdO, K, acc4);
+          if (line < a.nlines) {
+            gacc[1] += acc4[0];
+            gacc[2] += acc4[1];
+            gacc[3] += acc4[2];
+            gacc[4] += acc4[3];
+          }
+        } else {
+          nl_point<T>(p, V, K);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+      }
+    } else {
+      const T* cs = reinterpret_cast<const T*>(a.cs);
+      const cx<T>* kin_a = reinterpret_cast<const cx<T>*>(a.kin_a);
+      const cx<T>* kin_o = reinterpret_cast<const cx<T>*>(a.kin_o);
+      const cx<T>* kin_l = reinterpret_cast<const cx<T>*>(a.kin_l);
+      const T Om = T(a.Omega), ga = T(a.gamma), norm = T(a.norm);
+      // 1/N^d as a (hi, lo) pair: exact for powers of two, compensated otherwise
+      const T norm_lo = T(a.norm - (double)norm);
+      const int nxx = (int)a.ncols;
+      for (int pt = tid; pt < W * N; pt += NT) {
+        const int pc = pt / N, kl = pt % N;
+        const long kx = kx0 + pc < a.ncols ? kx0 + pc : 0;
+        const int px = (int)(kx < nxx / 2 ? kx : kx - nxx);
+        const T nup = T(px * a.nu_scale_a);
+        int kq;
+        long qidx;
+        cx<T> ka = kin_a[kx];
+        if (a.dim == 2) {
+          kq = kl;
+          qidx = (long)kl * nxx + kx;
+        } else {
+          kq = (int)o;
+          qidx = o * nxx + kx;
+          const cx<T> ko = kin_o[o];
+          ka = ka + ko + ka * ko;
+        }
+        const int pq = kq < a.n_q / 2 ? kq : kq - a.n_q;
+        const T nuq = T(pq * a.nu_scale_q);
+        const T Cm1 = cs[2 * qidx], S = cs[2 * qidx + 1];
+        // alpha - 1 = (C - 1) - i S Omega; beta = i S gamma a = S gamma (nu_p - i nu_q)
+        const cx<T> as = mk<T>(Cm1, -S * Om);
+        const cx<T> beta = mk<T>(S * ga * nup, -S * ga * nuq);
+        const cx<T> kl1 = kin_l[kl];
+        const cx<T> ss = ka + kl1 + ka * kl1;  // kinetic phase - 1
+        cx<T> p[5];
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc)
+          p[cc] = mk<T>(kmul<T>(norm, norm_lo, lre[pt * 5 + cc]), kmul<T>(norm, norm_lo, lim[pt * 5 + cc]));
+        if constexpr (KIND == C_ADJ) {
+          // P^H = P(-d): same (C - 1), S -> -S, conjugate kinetic phase
+          sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
+          if (kx0 + pc < a.ncols) {
+            // m_a = -d Im(L^H f_a H), L = P^H L'/N^d (p), H the stored forward input
+            const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + o * a.outer_stride + kx * 5 + (long)kl * a.stride;
+            const double w4[4] = {1.0, 1.22474487139158904909864203735294570, 1.22474487139158904909864203735294570, 1.0};
+            double upr = 0, upi = 0, umr = 0, umi = 0, uzi = 0;
+            cx<T> hq[5];
+#pragma unroll
+            for (int cc = 0; cc < 5; ++cc) hq[cc] = fw[cc];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              const cx<T> a1 = cmulc(p[l], hq[l + 1]), a2 = cmulc(p[l + 1], hq[l]);
+              upr += 2.0 * w4[l] * a1.re; upi += 2.0 * w4[l] * a1.im;
+              umr += 2.0 * w4[l] * a2.re; umi += 2.0 * w4[l] * a2.im;
+            }
+#pragma unroll
+            for (int l = 0; l < 5; ++l) uzi += (2 - l) * (double)cmulc(p[l], hq[l]).im;
+            const double dd = a.d;
+            const double mx = -dd * 0.5 * (upi + umi);
+            const double my = dd * 0.5 * (upr - umr);
+            const double mz = -dd * uzi;
+            // dJ/dn = J_r(-d n)^T m, n = (gamma Re a, -gamma Im a, -Omega), a = -nu_q - i nu_p
+            const double nupd = px * a.nu_scale_a, nuqd = pq * a.nu_scale_q;
+            const double ox = -dd * a.gamma * (-nuqd), oy = -dd * (-a.gamma) * (-nupd), oz = -dd * (-a.Omega);
+            const double th2 = ox * ox + oy * oy + oz * oz;
+            double ja, jb;
+            if (th2 < 1e-8) { ja = 0.5 - th2 / 24.0; jb = 1.0 / 6.0 - th2 / 120.0; }
+            else {
+              const double th = sqrt(th2), hs = sin(0.5 * th);
+              ja = 2.0 * hs * hs / th2;
+              jb = (th - sin(th)) / (th2 * th);
+            }
+            const double cx1 = oy * mz - oz * my, cy1 = oz * mx - ox * mz, cz1 = ox * my - oy * mx;
+            const double cx2 = oy * cz1 - oz * cy1, cy2 = oz * cx1 - ox * cz1, cz2 = ox * cy1 - oy * cx1;
+            const double Dx = mx + ja * cx1 + jb * cx2, Dy = my + ja * cy1 + jb * cy2, Dz = mz + ja * cz1 + jb * cz2;
+            gacc[0] += -nuqd * Dx + nupd * Dy;  // dn/dgamma = (Re a, -Im a, 0) = (-nu_q, nu_p, 0)
+            gacc[1] += -Dz;                     // dn/dOmega = (0, 0, -1)
+          }
+        } else {
+          sym4_apply_inc<T>(as, beta, ss, p);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int o5 = (col * N + t + TL * m) * 5 + c;
+      v[0][m] = mk<T>(lre[o5], lim[o5]);
+    }
+    __syncthreads();
+  }
+
+  if constexpr (KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST)
+    fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+  if constexpr (KIND == C_PROP || KIND == C_ADJ) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+
+  if constexpr (ADJ) {
+    // parameter partials: block reduction in a fixed order into this block's slot
+#pragma unroll
+    for (int q = 0; q < NGRAD; ++q) {
+      double vq = gacc[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) vq += __shfl_down(vq, off, 64);
+      if ((tid & 63) == 0) gred[tid >> 6][q] = vq;
+    }
+    __syncthreads();
+    if (tid < NGRAD) {
+      double sum = 0.0;
+      for (int wv = 0; wv < (NT + 63) / 64; ++wv) sum += gred[wv][tid];
+      a.gacc[(long)blockIdx.x * NGRAD + tid] += sum;
+    }
+  }
+
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
+  }
+  if constexpr (XL && !ADJ) {
+    if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) {
+      a.clock[0] = a.s_arg;
+      double sn, cn;
+      sincos(a.Omega * a.s_arg, &sn, &cn);
+      a.clock[1] = cn;
+      a.clock[2] = sn;
+    }
+  }
+  if constexpr (KIND == C_PROP) {
+    if (a.advance_clock && tile == 0 && tid == 0) {
+      const double s1 = a.clock[0] + a.d;
+      double sn, cn;
+      sincos(a.Omega * s1, &sn, &cn);
+      a.clock[0] = s1;
+      a.clock[1] = cn;
+      a.clock[2] = sn;
+    }
+  }
+}
+
+template <typename T, int N, int E, int W, int KIND>
+__global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ psi, PassArgs a) {
+  constexpr int BUF = pass_lds<N, W, KIND>();
+  constexpr int NT = W * 5 * (N / E);
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double gred[KindInfo<KIND>::ADJ ? NT / 64 + 1 : 1][NGRAD];
+  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lre, lim, gred);
+}
+
+// ---------------------------------------------------------------------------
+// Batched pass over many grids (an ensemble): block b processes work item
+// items[b] = (instance, tile) with that instance's arguments; every line length
+// used runs with 320 threads per block (W = 64 E / N lines per block).
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
+  constexpr int BUF = pass_lds<384, 2, KIND>() > pass_lds<512, 1, KIND>() ? pass_lds<384, 2, KIND>()
+                                                                           : pass_lds<512, 1, KIND>();
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double gred[KindInfo<KIND>::ADJ ? 6 : 1][NGRAD];
+  const int2 it = items[blockIdx.x];
+  const PassArgs& a = args[it.x];
+  cx<T>* psi = reinterpret_cast<cx<T>*>(a.state);
+  switch (a.n_line) {
+    case 64: pass_body<T, 64, 8, 8, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 128: pass_body<T, 128, 8, 4, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 256: pass_body<T, 256, 8, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 384: pass_body<T, 384, 12, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 512: pass_body<T, 512, 8, 1, KIND>(psi, a, it.y, lre, lim, gred); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Observables (Sec. 2) on the physical state, FP64 partial sums per block.
+// OBS_X (lines along x): d_x psi spectrally; per point the mass, the
+//   magnetization, V|psi|^2, the interaction energy, |d_x psi|^2/2,
+//   Re(conj(psi) i y d_x psi) (the y d_x part of -i(x d_y - y d_x)) and
+//   Re(psi^H K d_x psi);
+// OBS_Y / OBS_Z (columns): d_y psi (or d_z psi); |d psi|^2/2,
+//   Re(conj(psi) (-i x) d_y psi) and Re(i psi^H M d_y psi) (y only).
+// With L+- = i d_y +- d_x the SOC matrix is S = i d_y M + d_x K, M symmetric with
+// the weights (1, sqrt6/2, sqrt6/2, 1) on both off-diagonals, K = -M above and +M
+// below the diagonal.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int E, int W, int KIND>
+__global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict__ psi, PassArgs a,
+                                                         double* __restrict__ part) {
+  constexpr int TL = N / E;
+  constexpr int NT = W * 5 * TL;
+  constexpr int LS = PadLine<N>::size;
+  constexpr bool XL = KIND == OBS_X;
+  constexpr int TILE = 2 * W * N * 5;
+  constexpr int XCH = W * 5 * LS;
+  constexpr int BUF = TILE > XCH ? TILE : XCH;
+  __shared__ T lre[BUF];
+  __shared__ T lim[BUF];
+  __shared__ double red[NT / 64 + 1][NOBS];
+
+  const int tid = threadIdx.x;
+  const int c = tid % 5;
+  const int rest = tid / 5;
+  const int col = XL ? rest / TL : rest % W;
+  const int t = XL ? rest % TL : rest / W;
+  const long tile = blockIdx.x;
+  long base, estride, line0 = 0, o = 0, kx0 = 0;
+  bool active;
+  if constexpr (XL) {
+    line0 = tile * W;
+    const long line = line0 + col;
+    active = line < a.nlines;
+    base = (active ? line : 0) * (long)N * 5;
+    estride = 5;
+  } else {
+    const long ncolblk = (a.ncols + W - 1) / W;
+    o = tile / ncolblk;
+    kx0 = (tile % ncolblk) * W;
+    const long kx = kx0 + col;
+    active = kx < a.ncols;
+    base = o * a.outer_stride + (active ? kx : 0) * 5;
+    estride = a.stride;
+  }
+  cx<T> v[1][E], f[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
+    f[m] = v[0][m];
+  }
+  T* xre = lre + (col * 5 + c) * LS;
+  T* xim = lim + (col * 5 + c) * LS;
+  // derivative along the line: FFT, multiply by i nu / N, inverse FFT
+  fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + TL * m;
+    const int p = k < N / 2 ? k : k - N;
+    const T nu = T(p * a.nu_scale_l / N);
+    v[0][m] = mk<T>(-nu * v[0][m].im, nu * v[0][m].re);
+  }
+  fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
+  // tile: psi at [0, W N 5), derivative at [W N 5, 2 W N 5)
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int o5 = (col * N + t + TL * m) * 5 + c;
+    lre[o5] = f[m].re;
+    lim[o5] = f[m].im;
+    lre[W * N * 5 + o5] = v[0][m].re;
+    lim[W * N * 5 + o5] = v[0][m].im;
+  }
+  __syncthreads();
+  double acc[NOBS];
+#pragma unroll
+  for (int q = 0; q < NOBS; ++q) acc[q] = 0.0;
+  const double h6 = 1.22474487139158904909864203735294570;
+  const double w[4] = {1.0, h6, h6, 1.0};  // weights of the links (l, l-1), l = 2..-1
+  double ct = 1.0, st = 0.0;
+  if constexpr (XL) sincos(a.Omega * a.s_arg, &st, &ct);
+  for (int pt = tid; pt < W * N; pt += NT) {
+    const int pc = pt / N, j = pt % N;
+    bool on;
+    double x, y, z;
+    if constexpr (XL) {
+      const long line = line0 + pc;
+      on = line < a.nlines;
+      const int iy = (int)(line % a.ny), iz = (int)(line / a.ny);
+      x = -a.L[0] + j * a.h[0];
+      y = -a.L[1] + iy * a.h[1];
+      z = -a.L[2] + iz * a.h[2];
+    } else {
+      on = kx0 + pc < a.ncols;
+      x = -a.L[0] + (kx0 + pc) * a.h[0];
+      y = z = 0.0;
+    }
+    if (!on) continue;
+    double pr[5], pi[5], dr[5], di[5];
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      pr[cc] = lre[pt * 5 + cc];
+      pi[cc] = lim[pt * 5 + cc];
+      dr[cc] = lre[W * N * 5 + pt * 5 + cc];
+      di[cc] = lim[W * N * 5 + pt * 5 + cc];
+    }
+    double grad2 = 0.0, rot = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      grad2 += dr[cc] * dr[cc] + di[cc] * di[cc];
+      rot += pr[cc] * di[cc] - pi[cc] * dr[cc];  // Im(conj(psi) d psi)
+    }
+    if constexpr (XL) {
+      double n[5], rho = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc) { n[cc] = pr[cc] * pr[cc] + pi[cc] * pi[cc]; rho += n[cc]; }
+      const double mg = 2.0 * (n[0] - n[4]) + (n[1] - n[3]);
+      const double X = ct * x + st * y, Y = -st * x + ct * y;
+      const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y + a.g2[2] * z * z);
+      // F_+ = 2 (conj(p2) p1 + conj(p-1) p-2) + sqrt6 (conj(p1) p0 + conj(p0) p-1)
+      double fr = 0.0, fi = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        fr += 2.0 * w[l] * (pr[l] * pr[l + 1] + pi[l] * pi[l + 1]);
+        fi += 2.0 * w[l] * (pr[l] * pi[l + 1] - pi[l] * pr[l + 1]);
+      }
+      // A00 = (2 p2 p-2 - 2 p1 p-1 + p0^2)/sqrt5
+      const double ar = (2.0 * (pr[0] * pr[4] - pi[0] * pi[4]) - 2.0 * (pr[1] * pr[3] - pi[1] * pi[3]) +
+                         (pr[2] * pr[2] - pi[2] * pi[2])) * 0.44721359549995793928;
+      const double ai = (2.0 * (pr[0] * pi[4] + pi[0] * pr[4]) - 2.0 * (pr[1] * pi[3] + pi[1] * pr[3]) +
+                         2.0 * pr[2] * pi[2]) * 0.44721359549995793928;
+      const double eint = 0.5 * a.c0 * rho * rho + 0.5 * a.c1 * (fr * fr + fi * fi + mg * mg) +
+                          0.5 * a.c2 * (ar * ar + ai * ai);
+      // Re psi^H K d_x psi: -w conj(p_l) d p_(l+1) + w conj(p_(l+1)) d p_l
+      double soc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        soc += w[l] * (-(pr[l] * dr[l + 1] + pi[l] * di[l + 1]) + (pr[l + 1] * dr[l] + pi[l + 1] * di[l]));
+      acc[0] += rho;
+      acc[1] += mg;
+      acc[2] += V * rho;
+      acc[3] += eint;
+      acc[4] += 0.5 * grad2;
+      acc[5] += -y * rot;  // Re(conj(psi) (i y) d_x psi)
+      acc[6] += soc;
+    } else {
+      acc[4] += 0.5 * grad2;
+      if constexpr (KIND == OBS_Y) {
+        acc[5] += x * rot;  // Re(conj(psi) (-i x) d_y psi)
+        // Re(i psi^H M d_y psi) = -Im(psi^H M d_y psi)
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+          s += w[l] * ((pr[l] * di[l + 1] - pi[l] * dr[l + 1]) + (pr[l + 1] * di[l] - pi[l + 1] * dr[l]));
+        acc[6] += -s;
+      }
+    }
+  }
+  // block reduction in a fixed order
+#pragma unroll
+  for (int q = 0; q < NOBS; ++q) {
+    double vq = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vq += __shfl_down(vq, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6][q] = vq;
+  }
+  __syncthreads();
+  if (tid < NOBS) {
+    double s = 0.0;
+    for (int wv = 0; wv < (NT + 63) / 64; ++wv) s += red[wv][tid];
+    part[(long)blockIdx.x * NOBS + tid] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Propagator table, FP64: Q = n.f with n = (gamma Re a, -gamma Im a, -Omega), so
+// exp(i d Q) is the spin-2 image of exp(i d n.sigma/2) = C + i S n.sigma with
+// C = cos(lam d/2), S = sin(lam d/2)/lam, lam = |n| = sqrt(Omega^2 + gamma^2
+// (nu_p^2 + nu_q^2)).  Stored per (p, q), rounded to T: (C - 1, S), with
+// C - 1 = -2 sin^2(lam d/4).  Kinetic tables per axis: exp(-i d nu^2/2) - 1.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_build_cs(T* __restrict__ cs, int nx, int ny, double Lx, double Ly, double Omega, double gamma,
+                           double d) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)nx * ny) return;
+  const int kx = (int)(i % nx), ky = (int)(i / nx);
+  const int p = kx < nx / 2 ? kx : kx - nx;
+  const int q = ky < ny / 2 ? ky : ky - ny;
+  const double pi = 3.14159265358979323846264338327950288;
+  const double nup = pi * p / Lx, nuq = pi * q / Ly;
+  const double lam = sqrt(Omega * Omega + gamma * gamma * (nup * nup + nuq * nuq));
+  double Cm1, S;
+  if (lam == 0.0) {
+    Cm1 = 0.0;
+    S = 0.5 * d;
+  } else {
+    const double s4 = sin(0.25 * lam * d);
+    Cm1 = -2.0 * s4 * s4;
+    S = sin(0.5 * lam * d) / lam;
+  }
+  cs[2 * i] = (T)Cm1;
+  cs[2 * i + 1] = (T)S;
+}
+
+template <typename T>
+__global__ void k_build_kin(cx<T>* __restrict__ kin, int n, double L, double d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int p = k < n / 2 ? k : k - n;
+  const double nu = 3.14159265358979323846264338327950288 * p / L;
+  const double ph = -0.5 * d * nu * nu;
+  const double sh = sin(0.5 * ph);
+  kin[k].re = (T)(-2.0 * sh * sh);
+  kin[k].im = (T)sin(ph);
+}
+
+
+// ---------------------------------------------------------------------------
+// Launch geometry of a register plan (N, E): TL = N/E threads per line and
+// component; W lines per block so that a block has 320 threads (W = 64/TL), or one
+// line of 5 TL threads when TL > 64.  Every instantiation of a plan (alone or in
+// an ensemble) uses this geometry, so its results do not depend on the caller.
+// ---------------------------------------------------------------------------
+template <int N, int E>
+struct Geo {
+  static constexpr int TL = N / E;
+  static constexpr int W = TL >= 64 ? 1 : 64 / TL;
+  static constexpr int NT = W * 5 * TL;
+};
+
+template <typename T, int N, int E, int KIND>
+static hipError_t pass_n(cx<T>* psi, const PassArgs& a, hipStream_t st) {
+  constexpr int W = Geo<N, E>::W;
+  constexpr bool XL = KindInfo<KIND>::XL;
+  long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
+  hipLaunchKernelGGL((k_pass<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(Geo<N, E>::NT), 0, st, psi, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int E>
+static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t st) {
+  switch (kind) {
+    case X_FIRST: return pass_n<T, N, E, X_FIRST>(psi, a, st);
+    case X_MID: return pass_n<T, N, E, X_MID>(psi, a, st);
+    case X_LAST: return pass_n<T, N, E, X_LAST>(psi, a, st);
+    case X_NLONLY: return pass_n<T, N, E, X_NLONLY>(psi, a, st);
+    case C_PROP: return pass_n<T, N, E, C_PROP>(psi, a, st);
+    case C_FWD: return pass_n<T, N, E, C_FWD>(psi, a, st);
+    case C_INV: return pass_n<T, N, E, C_INV>(psi, a, st);
+    case XA_FIRST: return pass_n<T, N, E, XA_FIRST>(psi, a, st);
+    case XA_MID: return pass_n<T, N, E, XA_MID>(psi, a, st);
+    case XA_LAST: return pass_n<T, N, E, XA_LAST>(psi, a, st);
+    case C_ADJ: return pass_n<T, N, E, C_ADJ>(psi, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int N, int E, int KIND>
+static hipError_t obs_n(const cx<T>* psi, const PassArgs& a, double* part, hipStream_t st) {
+  constexpr int W = obs_lines_per_block(N, E);
+  constexpr bool XL = KIND == OBS_X;
+  long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
+  hipLaunchKernelGGL((k_obs<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(W * 5 * (N / E)), 0, st, psi, a,
+                     part);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int E>
+static hipError_t obs_kind(int kind, const cx<T>* psi, const PassArgs& a, double* part, hipStream_t st) {
+  switch (kind) {
+    case OBS_X: return obs_n<T, N, E, OBS_X>(psi, a, part, st);
+    case OBS_Y: return obs_n<T, N, E, OBS_Y>(psi, a, part, st);
+    default: return obs_n<T, N, E, OBS_Z>(psi, a, part, st);
+  }
+}
+
+// All pass and observables kernels of one register-plan width E (every supported
+// line length with that E).  Each (T, E) pair is compiled in its own translation
+// unit.
+#define SGP_FOR_PLAN_N(E, X)                                     \
+  X(16, E) X(32, E) X(64, E) X(128, E) X(256, E) X(384, E) X(512, E)
+
+template <typename T, int E>
+hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st) {
+  cx<T>* p = reinterpret_cast<cx<T>*>(psi);
+#define SGP_CASE(NN, EE) \
+  case NN:               \
+    if constexpr (plan_ok(NN, EE)) return pass_kind<T, NN, EE>(kind, p, a, st); \
+    break;
+  switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
+#undef SGP_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int E>
+hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, double* part, hipStream_t st) {
+  const cx<T>* p = reinterpret_cast<const cx<T>*>(psi);
+#define SGP_CASE(NN, EE) \
+  case NN:               \
+    if constexpr (plan_ok(NN, EE)) return obs_kind<T, NN, EE>(kind, p, a, part, st); \
+    break;
+  switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
+#undef SGP_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sgp

@@ -62,6 +62,11 @@ def lib():
     L.sgp_step_store.argtypes = [vp, vp, ctypes.c_long, vp, ctypes.c_size_t]
     L.sgp_adjoint_segment.argtypes = [vp, vp, ctypes.c_long, vp, ctypes.c_size_t]
     L.sgp_adjoint_gradients.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.sgp_plan_widths.argtypes = [ctypes.c_int, ip, ctypes.c_int]
+    L.sgp_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.sgp_get_plan.argtypes = [vp, ctypes.c_int, ip]
+    L.sgp_autotune.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
     L.sgp_destroy.argtypes = [vp]
     L.sgp_destroy.restype = None
     L.sgp_last_error.argtypes = [vp]
@@ -75,9 +80,24 @@ def exported_symbols():
     return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
             "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
+            "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune",
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
             "sgp_ensemble_last_error"]
+
+
+def plan_widths(n):
+    """Register plan widths E compiled for line length n (the default first)."""
+    out = (ctypes.c_int * 8)()
+    k = lib().sgp_plan_widths(int(n), out, 8)
+    if k < 0:
+        raise SgpError(f"unsupported line length {n}")
+    return list(out[:k])
+
+
+def plan_cache_path():
+    """JSON file of autotuned plans: $SGP_PLAN_CACHE, else ~/.cache/sgp/plans.json."""
+    return os.environ.get("SGP_PLAN_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "sgp", "plans.json")
 
 
 def _check(rc, ctx=None):
@@ -188,6 +208,62 @@ class Solver:
         out = (ctypes.c_double * 5)()
         _check(lib().sgp_adjoint_gradients(self._ctx, out, int(bool(reset))), self._ctx)
         return np.array(out[:])
+
+    def get_plan(self):
+        """Plan width E of the passes along x, y (, z)."""
+        e = ctypes.c_int()
+        out = []
+        for ax in range(len(self.shape)):
+            _check(lib().sgp_get_plan(self._ctx, ax, ctypes.byref(e)), self._ctx)
+            out.append(e.value)
+        return out
+
+    def set_plan(self, widths):
+        """Plan widths per axis (x, y (, z)); 0 = default."""
+        for ax, e in enumerate(widths):
+            _check(lib().sgp_set_plan(self._ctx, ax, int(e)), self._ctx)
+
+    def plan_key(self, scheme):
+        import torch
+        prop = torch.cuda.get_device_properties(self.device)
+        arch = getattr(prop, "gcnArchName", "") or prop.name
+        return f"{arch}|{'x'.join(map(str, self.shape))}|{str(self.torch_dtype).replace('torch.', '')}|TS{scheme}"
+
+    def autotune(self, psi, scheme, steps=20, cache=True):
+        """Pick the plan width of every axis (sgp_autotune on a scratch copy of psi)
+        and keep the choice in the JSON plan cache (plan_cache_path()); with cache,
+        a stored choice for this device, shape, dtype and scheme is applied without
+        timing.  Returns (widths, ms_per_step or None)."""
+        import json
+        key = self.plan_key(scheme)
+        path = plan_cache_path()
+        table = {}
+        if cache and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+            if key in table:
+                self.set_plan(table[key]["widths"])
+                return self.get_plan(), None
+        scratch = psi.clone()
+        out = (ctypes.c_int * 3)()
+        ms = ctypes.c_double()
+        _check(lib().sgp_autotune(self._ctx, self._psi_ptr(scratch), int(steps), out, ctypes.byref(ms)), self._ctx)
+        del scratch
+        widths = list(out[:len(self.shape)])
+        if cache:
+            table[key] = {"widths": widths, "ms_per_step": ms.value}
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                tmp = path + f".{os.getpid()}.tmp"
+                with open(tmp, "w") as f:
+                    json.dump(table, f, indent=1, sort_keys=True)
+                os.replace(tmp, path)
+            except OSError:
+                pass
+        return widths, ms.value
 
     def set_graph(self, on):
         _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)

@@ -75,3 +75,28 @@ def test_workspace_size_scales_with_grid_and_dtype():
         sizes[(n, dt)] = nb.value
         L.sgp_destroy(ctx)
     assert sizes[(64, 1)] > sizes[(64, 0)] and sizes[(256, 0)] > 10 * sizes[(64, 0)]
+
+
+def test_plan_widths_and_plan_setters_without_device():
+    L = sgp.lib()
+    for n, want in ((16, [8, 4]), (32, [8, 4]), (64, [8, 4, 16]), (128, [8, 4, 16]), (256, [8, 4, 16]),
+                    (512, [8, 4, 16]), (384, [12, 24])):
+        assert sgp.plan_widths(n) == want
+    out = (ctypes.c_int * 1)()
+    assert L.sgp_plan_widths(512, out, 1) == 3 and out[0] == 8  # count even when truncated
+    assert L.sgp_plan_widths(48, out, 1) == -1
+    rc, ctx = _create(n=(512, 64, 1))
+    assert rc == 0
+    e = ctypes.c_int()
+    assert L.sgp_get_plan(ctx, 0, ctypes.byref(e)) == 0 and e.value == 8
+    assert L.sgp_set_plan(ctx, 0, 4) == 0
+    assert L.sgp_get_plan(ctx, 0, ctypes.byref(e)) == 0 and e.value == 4
+    assert L.sgp_set_plan(ctx, 1, 16) == 0
+    assert L.sgp_set_plan(ctx, 1, 12) == -1 and b"not available" in L.sgp_last_error(ctx)
+    assert L.sgp_set_plan(ctx, 2, 8) == -1  # 2D: no z axis
+    assert L.sgp_set_plan(ctx, 0, 0) == 0
+    assert L.sgp_get_plan(ctx, 0, ctypes.byref(e)) == 0 and e.value == 8
+    outw = (ctypes.c_int * 3)()
+    assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 5, outw, None) == -2  # no workspace yet
+    assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 0, outw, None) == -1
+    L.sgp_destroy(ctx)
