@@ -402,7 +402,8 @@ int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   if (e != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, e, "event create"); }
   e = hipEventRecord(e0, c->st);
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
-    if (pass == 0) e = run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], CLOCK_ARG, c->t);
+    // X-pass as inside a step: the clock from the device slots (set by the first launch)
+    if (pass == 0) e = run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], i == 0 ? CLOCK_ARG : CLOCK_DEVICE, c->t);
     else if (pass == 1) e = run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0);
     else if (pass == 2) e = run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0);
     else e = run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0);

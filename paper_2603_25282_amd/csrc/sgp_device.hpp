@@ -38,6 +38,27 @@ template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx
   return mk<T>(acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re);
 }
 
+// 1/x.  FP32: the hardware reciprocal estimate (within 1 ulp) refined by one Newton
+// step; FP64: division.  Used only on magnitudes bounded away from 0 and infinity.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 4) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, y, 1.0f), y, y);
+  } else {
+    return T(1) / x;
+  }
+}
+
+// Square root of x >= 0.  FP32: the hardware square root (within 1 ulp; the results
+// only set small rotation angles); FP64: sqrt.
+template <typename T>
+__device__ __forceinline__ T sqrt_nn(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_sqrtf(x);
+  else return sqrt(x);
+}
+
+
 // ---------------------------------------------------------------------------
 // Small DFT kernels, y_q = sum_s x_s exp(SIGN 2 pi i s q / R), in place.
 // ---------------------------------------------------------------------------
@@ -329,7 +350,7 @@ __device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, c
   cx<T> r, l;
   const cx<T> one = mk<T>(T(1), T(0));
   if (!pivot) {
-    const T q = T(1) / norm2(alpha);
+    const T q = recip(norm2(alpha));
     const cx<T> ia = mk<T>(alpha.re * q, -alpha.im * q);  // 1/alpha
     r = beta * ia;
     l = mk<T>(-beta.re, beta.im) * ia;  // -conj(beta)/alpha
@@ -337,7 +358,7 @@ __device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, c
     const cx<T> e2 = as * (mk<T>(T(2), T(0)) + as);
     const cx<T> e4 = e2 * (mk<T>(T(2), T(0)) + e2);
     const cx<T> one_e2 = one + e2;
-    const T q2 = T(1) / norm2(one_e2);
+    const T q2 = recip(norm2(one_e2));
     const cx<T> inv_e2 = mk<T>(one_e2.re * q2, -one_e2.im * q2);
     const cx<T> em2 = mk<T>(-e2.re, -e2.im) * inv_e2;
     const cx<T> em4 = em2 * (mk<T>(T(2), T(0)) + em2);
@@ -349,7 +370,7 @@ __device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, c
     eps[4] = em4 + ss + em4 * ss;
   } else {
     // U P = [[beta, alpha], [conj(alpha), -conj(beta)]], det -1
-    const T q = T(1) / norm2(beta);
+    const T q = recip(norm2(beta));
     const cx<T> ia = mk<T>(beta.re * q, -beta.im * q);  // 1/beta
     r = alpha * ia;
     l = conj(alpha) * ia;
@@ -413,6 +434,42 @@ __device__ __forceinline__ void cosm1_sinc(T x, T& cm1, T& sc) {
   }
 }
 
+// exp(-i phi) - 1 = (cos phi - 1) - i sin phi for an FP64 phase, both parts to full
+// FP64 accuracy without cancellation and without a general-range sin/cos: phi is
+// reduced mod 2 pi to r in [-pi, pi] (two-part 2 pi), q = r/4 lies in [-pi/4, pi/4],
+// where the Taylor series of sin q (to q^15) and cos q (to q^16) truncate below
+// 5e-17; then sin(r/2) = 2 sin q cos q gives
+//   cos phi - 1 = -2 sin^2(r/2) = -8 sin^2 q cos^2 q,
+//   sin phi = 2 sin(r/2) cos(r/2) = 4 sin q cos q (1 - 2 sin^2 q).
+__device__ __forceinline__ void phase_inc(double phi, double& cm1, double& sn) {
+  const double k = rint(phi * 0.15915494309189533576888376337251437);
+  double r = fma(-k, 6.283185307179586231995926937088370323, phi);
+  r = fma(-k, 2.449293598294706e-16, r);
+  const double q = 0.25 * r, q2 = q * q;
+  const double sq =
+      q * fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, -7.647163731819816475901131985788e-13,
+                                                                 1.605904383682161459939237717015e-10),
+                                                         -2.505210838544171877505210838544e-8),
+                                                 2.755731922398589065255731922399e-6),
+                                         -1.984126984126984126984126984127e-4),
+                                 8.333333333333333333333333333333e-3),
+                         -1.666666666666666666666666666667e-1),
+              1.0);
+  const double cq =
+      fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, fma(q2, 4.779477332387385297438207491118e-14,
+                                                                 -1.147074559772972471385169797868e-11),
+                                                         2.087675698786809897921009032120e-9),
+                                                 -2.755731922398589065255731922399e-7),
+                                         2.480158730158730158730158730159e-5),
+                                 -1.388888888888888888888888888889e-3),
+                         4.166666666666666666666666666667e-2),
+                 -0.5),
+          1.0);
+  const double sc = sq * cq;
+  cm1 = -8.0 * sc * sc;
+  sn = 4.0 * sc * fma(-2.0 * sq, sq, 1.0);
+}
+
 // ---------------------------------------------------------------------------
 // Exact nonlinear flow at one point for time d (Sec. 3.2, eq. solution2):
 //   b = cos(c2 S d) psi + i (sin(c2 S d)/S) (rho/5 psi - A00 A conj(psi))
@@ -444,7 +501,7 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
   const T rho5 = rho * T(0.2);
   T S2 = rho5 * rho5 - norm2(A00) * T(0.2);
   S2 = S2 > T(0) ? S2 : T(0);
-  const T S = sqrt(S2);
+  const T S = sqrt_nn(S2);
   const T c2d = T(K.c2 * K.d);
   T cm1, snc;
   cosm1_sinc<T>(c2d * S, cm1, snc);
@@ -460,7 +517,7 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
     b[i] = p[i] + (cm1 * p[i] + snS * mul_i(w));
   }
   // spin rotation: alpha - 1 = (cos(kappa/2) - 1) - i s F_z, beta = -i s F_-
-  const T Fabs = sqrt(norm2(Fp) + Fz * Fz);
+  const T Fabs = sqrt_nn(norm2(Fp) + Fz * Fz);
   const T hc1d = T(0.5 * K.c1 * K.d);
   T ckm1, skc;
   cosm1_sinc<T>(hc1d * Fabs, ckm1, skc);
@@ -468,13 +525,9 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
   const cx<T> as = mk<T>(ckm1, -s * Fz);
   const cx<T> beta = mk<T>(-s * Fp.im, -s * Fp.re);
   // scalar phase exp(-i phi) - 1, phi = d [V + (c0 + c2/5) rho], in FP64
-  const double phi = K.d * (V + K.c0p * (double)rho);
-  const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
-  const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
-  double sh, chh;
-  sincos(0.5 * red, &sh, &chh);
-  // exp(-i phi) - 1 = -2 sin^2(phi/2) - i sin(phi), sin(phi) = 2 sin(phi/2) cos(phi/2)
-  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-2.0 * sh * chh));
+  double pcm1, psn;
+  phase_inc(K.d * (V + K.c0p * (double)rho), pcm1, psn);
+  const cx<T> phs = mk<T>((T)pcm1, (T)(-psn));  // exp(-i phi) - 1
   sym4_apply_inc<T>(as, beta, phs, b);
 #pragma unroll
   for (int i = 0; i < 5; ++i) p[i] = b[i];
@@ -510,7 +563,7 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
   const T rho5 = rho * T(0.2);
   T S2 = rho5 * rho5 - norm2(A00) * T(0.2);
   S2 = S2 > T(0) ? S2 : T(0);
-  const T S = sqrt(S2);
+  const T S = sqrt_nn(S2);
   const T c2d = T(K.c2 * K.d);
   T cm1, snc;
   cosm1_sinc<T>(c2d * S, cm1, snc);
@@ -531,19 +584,16 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
     b[i] = p[i] + (cm1 * p[i] + Sig * mul_i(w[i]));
   }
   // rotation and phase (as in nl_point)
-  const T Fabs = sqrt(norm2(Fp) + Fz * Fz);
+  const T Fabs = sqrt_nn(norm2(Fp) + Fz * Fz);
   const T hc1d = T(0.5 * K.c1 * K.d);
   T ckm1, skc;
   cosm1_sinc<T>(hc1d * Fabs, ckm1, skc);
   const T sr = hc1d * skc;
   const cx<T> as = mk<T>(ckm1, -sr * Fz);
   const cx<T> beta = mk<T>(-sr * Fp.im, -sr * Fp.re);
-  const double phi = K.d * (V + K.c0p * (double)rho);
-  const double k2pi = rint(phi * 0.15915494309189533576888376337251437);
-  const double red = fma(-k2pi, 6.28318530717958647692528676655900577, phi);
-  double sh, chh;
-  sincos(0.5 * red, &sh, &chh);
-  const cx<T> phs = mk<T>((T)(-2.0 * sh * sh), (T)(-2.0 * sh * chh));
+  double pcm1, psn;
+  phase_inc(K.d * (V + K.c0p * (double)rho), pcm1, psn);
+  const cx<T> phs = mk<T>((T)pcm1, (T)(-psn));
   // psi' and h = exp(i phi) R^H g'
   cx<T> out[5], h[5];
 #pragma unroll

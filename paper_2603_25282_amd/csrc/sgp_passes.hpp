@@ -160,8 +160,12 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       trap_angle(a, ct, st);
       for (int pt = tid; pt < W * N; pt += NT) {
         const int pc = pt / N, j = pt % N;
-        const long line = line0 + pc;
-        const int iy = (int)(line % a.ny), iz = (int)(line / a.ny);
+        const int line = (int)line0 + pc;  // y + ny z (< 2^31 for every supported grid)
+        int iy = line, iz = 0;
+        if (a.dim == 3) {
+          iz = line / a.ny;
+          iy = line - iz * a.ny;
+        }
         const double x = -a.L[0] + j * a.h[0];
         const double y = -a.L[1] + iy * a.h[1];
         const double z = -a.L[2] + iz * a.h[2];

@@ -95,3 +95,40 @@ def test_workload_loss_gradients_fd_and_oracle():
         fd = (J_gpu(psi0, pp) - J_gpu(psi0, pm)) / (2 * eps)
         print("param", k, "fd", fd, "adjoint fp32", d32[k], "fp64", d64[k])
         assert abs(fd - d32[k]) <= 1e-4 * max(1e-3, abs(fd))
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_differentiation_workload_full(dtype):
+    # Full differentiation workload: 256^2 on [-12, 12]^2, TS4, tau = 1e-3, 500 steps,
+    # checkpoints every 50 steps; loss of tests/adjoint_loss.py.  Against the oracle's
+    # stored J, dJ/d(gamma, Omega, c0, c1, c2) and state-gradient samples
+    # (tests/golden/make_c5_reference.py calls only the oracle).
+    import os
+    import torch
+    from paper_2603_25282_amd.autograd import evolve
+    from paper_2603_25282_amd.sgp import Solver
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "c5_reference.npz"))
+    cfg = I.C5
+    psi0 = I.initial_state(cfg)
+    target = I.initial_state(I.with_(cfg, seed=cfg.extra["target_seed"]))
+    tdt = torch.complex64 if dtype == "complex64" else torch.complex128
+    dev = torch.device("cuda:0")
+    prm = cfg.params
+    print(f"case differentiation workload {cfg.shape} {dtype} steps={cfg.steps} K={cfg.extra['K']}", flush=True)
+    p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(tdt).to(dev).requires_grad_(True)
+    par = torch.tensor([prm[i] for i in PIDX], dtype=torch.float64, requires_grad=True)
+    out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, cfg.steps, order=cfg.order, K=cfg.extra["K"])
+    phi = Solver.from_device_layout(out.detach().cpu().numpy().astype(np.complex128))
+    J, gT = loss_and_grad(phi, target, cfg.L)
+    out.backward(torch.from_numpy(Solver.to_device_layout(gT)).to(tdt).to(dev))
+    g0 = Solver.from_device_layout(p0.grad.cpu().numpy().astype(np.complex128))
+    d = par.grad.numpy()
+    eg = rel_l2(g0.reshape(5, -1)[:, ref["idx"]], ref["g0_samples"])
+    eJ = abs(J - float(ref["J"])) / abs(float(ref["J"]))
+    ed = np.abs(d - ref["dpar"]) / np.abs(ref["dpar"])
+    print(f"J {J} (oracle {float(ref['J'])}, rel {eJ:.2e}); state grad rel l2 (samples) {eg:.2e}; "
+          f"dpar {d} (oracle {ref['dpar']}, rel {ed})", flush=True)
+    if dtype == "complex128":
+        assert eJ <= 1e-10 and eg <= 1e-10 and np.all(ed <= 1e-8)
+    else:
+        assert eJ <= 1e-4 and eg <= 1e-4 and np.all(ed <= 1e-3)
