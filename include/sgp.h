@@ -157,13 +157,13 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
  * transforms each (line, component) with n/E threads holding E elements each; E
  * fixes the radix sequence (E = 8: radix 8 with one radix-2/4 pass; E = 4: radix 4
  * with one radix-2 pass; E = 16: radix 8 with two butterflies per thread; 384:
- * E = 12 {3,4,4,4,2} or E = 24 {3,8,8,2}) and the block shape.  Every plan computes
+ * E = 12 {3,4,4,4,2} or, for SGP_C64 only, E = 24 {3,8,8,2}) and the block shape.  Every plan computes
  * the same transform (results differ by rounding only).  Defaults: E = 8, or 12
  * for 384.
  *
- * sgp_plan_widths: writes up to max_out widths available for length n (the
- *   default first) to out and returns how many there are; SGP_ERR_ARG for an
- *   unsupported n.
+ * sgp_plan_widths: writes up to max_out widths available for length n and
+ *   element type dtype (the default first) to out and returns how many there
+ *   are; SGP_ERR_ARG for an unsupported n or dtype.
  * sgp_set_plan: plan width of the passes along `axis` (0 = x, 1 = y, 2 = z);
  *   elems = 0 restores the default.  SGP_ERR_ARG if the width is not available
  *   for that axis's length.  Rewrites the twiddle tables in the workspace (if set)
@@ -178,7 +178,7 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
  *   the context time is left unchanged.  Writes the chosen widths to elems_out
  *   (0 for axes beyond dim) and, if ms_per_step is not NULL, the fastest time per
  *   step in ms.  The choice stays set on the context. */
-int sgp_plan_widths(int n, int* out, int max_out);
+int sgp_plan_widths(int n, int dtype, int* out, int max_out);
 int sgp_set_plan(sgp_ctx* ctx, int axis, int elems);
 int sgp_get_plan(const sgp_ctx* ctx, int axis, int* elems);
 int sgp_autotune(sgp_ctx* ctx, void* psi_dev, int steps, int elems_out[3], double* ms_per_step);

@@ -43,22 +43,23 @@ std::vector<int> plan_radices(int n, int e, bool fwd) {
 }
 
 // Plan widths compiled for line length n (the default first).
-std::vector<int> plan_widths(int n) {
+std::vector<int> plan_widths(int n, int esize) {
   std::vector<int> out{default_elems(n)};
   for (int e : kPlanElems)
-    if (e != default_elems(n) && plan_ok(n, e)) out.push_back(e);
+    if (e != default_elems(n) && plan_ok(n, e, esize)) out.push_back(e);
   return out;
 }
 
-// Twiddle table of a plan: for each pass with NS > 1, for k in [0, NS), the values
-// exp(-2 pi i r k / (NS R)), r = 1..R-1 (the kernels conjugate them for the inverse).
+// Twiddle table of a plan: for each pass with NS > 1, for r = 1..R-1 and k in
+// [0, NS), the values exp(-2 pi i r k / (NS R)) (the kernels conjugate them for the
+// inverse).
 std::vector<std::complex<double>> twiddle_table(const std::vector<int>& radices) {
   std::vector<std::complex<double>> out;
   int ns = 1;
   for (int R : radices) {
     if (ns > 1)
-      for (int k = 0; k < ns; ++k)
-        for (int r = 1; r < R; ++r) {
+      for (int r = 1; r < R; ++r)
+        for (int k = 0; k < ns; ++k) {
           double a = -2.0 * kPi * (double)r * (double)k / (double)(ns * R);
           out.emplace_back(std::cos(a), std::sin(a));
         }
@@ -424,7 +425,7 @@ template <typename T>
 int set_plan_impl(sgp_ctx* c, int axis, int e) {
   if (axis < 0 || axis >= c->g.dim) return fail(c, SGP_ERR_ARG, "axis out of range");
   if (e == 0) e = default_elems(c->g.n[axis]);
-  if (!plan_ok(c->g.n[axis], e))
+  if (!plan_ok(c->g.n[axis], e, (int)c->esize))
     return fail(c, SGP_ERR_ARG, "plan width " + std::to_string(e) + " not available for length " +
                                     std::to_string(c->g.n[axis]));
   if (c->plan_e[axis] == e) return SGP_OK;
@@ -469,7 +470,7 @@ int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_m
   for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) {
     const int start = c->plan_e[ax];
     int best_e = start;
-    for (int e : plan_widths(c->g.n[ax])) {
+    for (int e : plan_widths(c->g.n[ax], (int)c->esize)) {
       if (e == start) continue;
       double ms = 0.0;
       rc = set_plan_impl<T>(c, ax, e);
@@ -647,7 +648,7 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
       // room for the largest table over the plans of this axis (plans can change later)
       size_t most = 0;
       if (ax < c->g.dim)
-        for (int e : plan_widths(c->g.n[ax]))
+        for (int e : plan_widths(c->g.n[ax], (int)c->esize))
           most = std::max(most, twiddle_table(plan_radices(c->g.n[ax], e, dir == 0)).size());
       if (ax < c->g.dim) off += align256(4 * c->esize * (most + 1));
     }
@@ -667,7 +668,7 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   // over every plan
   long maxb = 0;
   for (int axis = 0; axis < c->g.dim; ++axis)
-    for (int e : plan_widths(c->g.n[axis]))
+    for (int e : plan_widths(c->g.n[axis], (int)c->esize))
       maxb = std::max(maxb, std::max(obs_nblocks(c, axis, e), pass_nblocks(c, axis, e)));
   off += align256(sizeof(double) * NOBS * maxb);
   const long gb = maxb;
@@ -824,9 +825,9 @@ int sgp_adjoint_gradients(sgp_ctx* c, double out[5], int reset) {
   return SGP_OK;
 }
 
-int sgp_plan_widths(int n, int* out, int max_out) {
-  if (!supported_n(n) || (max_out > 0 && !out)) return SGP_ERR_ARG;
-  std::vector<int> w = plan_widths(n);
+int sgp_plan_widths(int n, int dtype, int* out, int max_out) {
+  if (!supported_n(n) || (max_out > 0 && !out) || (dtype != SGP_C64 && dtype != SGP_C128)) return SGP_ERR_ARG;
+  std::vector<int> w = plan_widths(n, dtype == SGP_C64 ? 4 : 8);
   for (int i = 0; i < (int)w.size() && i < max_out; ++i) out[i] = w[i];
   return (int)w.size();
 }

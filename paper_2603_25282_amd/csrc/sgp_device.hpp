@@ -214,8 +214,9 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre,
       const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cx<T> z = tw[2 * (k * (R - 1) + (r - 1))];
-        cx<T> zl = tw[2 * (k * (R - 1) + (r - 1)) + 1];
+        // table order [r - 1][k]: adjacent lanes (adjacent k) read adjacent entries
+        cx<T> z = tw[2 * ((r - 1) * NS + k)];
+        cx<T> zl = tw[2 * ((r - 1) * NS + k) + 1];
         w[b][r - 1] = SIGN < 0 ? z : conj(z);
         wl[b][r - 1] = SIGN < 0 ? zl : conj(zl);
       }
@@ -290,6 +291,46 @@ template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = R
 // 384 = 3 * 2^7: E = 12 (default) and E = 24
 template <> struct Plan<384, 12> { using fwd = RadixList<3, 4, 4, 4, 2>; using inv = RadixList<2, 4, 4, 4, 3>; };
 template <> struct Plan<384, 24> { using fwd = RadixList<3, 8, 8, 2>; using inv = RadixList<2, 8, 8, 3>; };
+
+// Twiddle-table entries of a plan direction: NS (R - 1) per pass with NS > 1 (each
+// entry is a (hi, lo) pair of cx<T>).
+template <int... Rs>
+constexpr int tw_entries(RadixList<Rs...>) {
+  int ns = 1, n = 0;
+  ((n += (ns > 1 ? ns * (Rs - 1) : 0), ns *= Rs), ...);
+  return n;
+}
+template <int... Rs>
+constexpr int n_passes(RadixList<Rs...>) { return (int)sizeof...(Rs); }
+template <int N, int E>
+struct TwSize {
+  static constexpr int fwd = tw_entries(typename Plan<N, E>::fwd{});
+  static constexpr int inv = tw_entries(typename Plan<N, E>::inv{});
+  // the first pass has no twiddles and ends with an exchange (a block barrier), so
+  // tables staged in LDS before the transform are visible when first read
+  static_assert(n_passes(typename Plan<N, E>::fwd{}) >= 2, "plans have at least two passes");
+};
+
+// Copy NCX cx<T> values (a whole twiddle table) from global memory to LDS with the
+// NT threads of a block, in 16-byte pieces, all loads issued before any store (named
+// registers, not an array, so that nothing lands in scratch memory).
+template <typename T, int NT, int NCX>
+__device__ __forceinline__ void stage_tw(cx<T>* __restrict__ dst, const void* __restrict__ src, int tid) {
+  constexpr int NCH = NCX * (int)sizeof(cx<T>) / 16;
+  static_assert(NCX * sizeof(cx<T>) % 16 == 0, "tables are whole 16-byte pieces");
+  static_assert(NCH <= 4 * NT, "at most four pieces per thread");
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  uint4 t0 = {}, t1 = {}, t2 = {}, t3 = {};
+  if (tid < NCH) t0 = s[tid];
+  if (NCH > NT && tid + NT < NCH) t1 = s[tid + NT];
+  if (NCH > 2 * NT && tid + 2 * NT < NCH) t2 = s[tid + 2 * NT];
+  if (NCH > 3 * NT && tid + 3 * NT < NCH) t3 = s[tid + 3 * NT];
+  if (tid < NCH) d[tid] = t0;
+  if (NCH > NT && tid + NT < NCH) d[tid + NT] = t1;
+  if (NCH > 2 * NT && tid + 2 * NT < NCH) d[tid + 2 * NT] = t2;
+  if (NCH > 3 * NT && tid + 3 * NT < NCH) d[tid + 3 * NT] = t3;
+}
 
 template <typename T, int N, int E, int SIGN, int NS, int NC, int NBUF, int SYNC, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,

@@ -15,7 +15,7 @@ SGP_EXTERN(double, 4) SGP_EXTERN(double, 8) SGP_EXTERN(double, 12) SGP_EXTERN(do
 
 template <typename T>
 hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st) {
-  if (!plan_ok(n, e)) return hipErrorInvalidValue;
+  if (!plan_ok(n, e, (int)sizeof(T))) return hipErrorInvalidValue;
   switch (e) {
     case 4: return launch_pass_e<T, 4>(kind, psi, a, n, st);
     case 8: return launch_pass_e<T, 8>(kind, psi, a, n, st);
@@ -28,7 +28,7 @@ hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hip
 
 template <typename T>
 hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e, double* part, hipStream_t st) {
-  if (!plan_ok(n, e)) return hipErrorInvalidValue;
+  if (!plan_ok(n, e, (int)sizeof(T))) return hipErrorInvalidValue;
   switch (e) {
     case 4: return launch_obs_e<T, 4>(kind, psi, a, n, part, st);
     case 8: return launch_obs_e<T, 8>(kind, psi, a, n, part, st);

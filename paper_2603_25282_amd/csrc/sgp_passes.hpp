@@ -65,7 +65,18 @@ template <int KIND> struct KindInfo {
   static constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
   static constexpr bool ADJ = XADJ || KIND == C_ADJ;
   static constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
+  // which transforms the pass runs (forward: exp(-i..), inverse: exp(+i..))
+  static constexpr bool HF = KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST ||
+                             KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ;
+  static constexpr bool HI = KIND == X_MID || KIND == X_LAST || KIND == XA_FIRST || KIND == XA_MID ||
+                             KIND == C_PROP || KIND == C_INV || KIND == C_ADJ;
 };
+
+// LDS cx<T> values of the staged twiddle tables of a pass (forward table first).
+template <int N, int E, int KIND>
+constexpr int pass_tw() {
+  return (KindInfo<KIND>::HF ? 2 * TwSize<N, E>::fwd : 0) + (KindInfo<KIND>::HI ? 2 * TwSize<N, E>::inv : 0);
+}
 
 // LDS elements (per re / im array) a pass needs.
 template <int N, int W, int KIND>
@@ -78,7 +89,7 @@ constexpr int pass_lds() {
 // Body of one block of a pass over `tile` (W lines), with caller-provided LDS.
 template <typename T, int N, int E, int W, int KIND>
 __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArgs& a, long tile, T* lre, T* lim,
-                                          double (*gred)[NGRAD]) {
+                                          cx<T>* ltw, double (*gred)[NGRAD]) {
   constexpr int TL = N / E;
   constexpr int NT = W * 5 * TL;
   constexpr int LS = PadLine<N>::size;
@@ -117,6 +128,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
     estride = a.stride;
   }
 
+  // unconditional loads (an inactive thread's base is a valid line), then masked
   cx<T> v[1][E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
@@ -124,8 +136,13 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
 
   T* xre = lre + (col * 5 + c) * LS;
   T* xim = lim + (col * 5 + c) * LS;
-  const cx<T>* twf = reinterpret_cast<const cx<T>*>(a.tw_fwd);
-  const cx<T>* twi = reinterpret_cast<const cx<T>*>(a.tw_inv);
+  // twiddle tables staged in LDS while the state loads are in flight
+  constexpr int TWF = KindInfo<KIND>::HF ? 2 * TwSize<N, E>::fwd : 0;
+  constexpr int TWI = KindInfo<KIND>::HI ? 2 * TwSize<N, E>::inv : 0;
+  const cx<T>* twf = ltw;
+  const cx<T>* twi = ltw + TWF;
+  if constexpr (TWF > 0) stage_tw<T, NT, TWF>(ltw, a.tw_fwd, tid);
+  if constexpr (TWI > 0) stage_tw<T, NT, TWI>(ltw + TWF, a.tw_inv, tid);
 
   if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID)
     fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
@@ -340,10 +357,13 @@ template <typename T, int N, int E, int W, int KIND>
 __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ psi, PassArgs a) {
   constexpr int BUF = pass_lds<N, W, KIND>();
   constexpr int NT = W * 5 * (N / E);
+  constexpr int TWB = (pass_tw<N, E, KIND>() * (int)sizeof(cx<T>) + 15) / 16;
   __shared__ T lre[BUF];
   __shared__ T lim[BUF];
+  __shared__ uint4 ltw[TWB > 0 ? TWB : 1];
   __shared__ double gred[KindInfo<KIND>::ADJ ? NT / 64 + 1 : 1][NGRAD];
-  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lre, lim, gred);
+  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lre, lim, reinterpret_cast<cx<T>*>(ltw),
+                              gred);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,18 +375,22 @@ template <typename T, int KIND>
 __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
   constexpr int BUF = pass_lds<384, 2, KIND>() > pass_lds<512, 1, KIND>() ? pass_lds<384, 2, KIND>()
                                                                            : pass_lds<512, 1, KIND>();
+  constexpr int TW1 = pass_tw<512, 8, KIND>(), TW2 = pass_tw<384, 12, KIND>();
+  constexpr int TWB = ((TW1 > TW2 ? TW1 : TW2) * (int)sizeof(cx<T>) + 15) / 16;
   __shared__ T lre[BUF];
   __shared__ T lim[BUF];
+  __shared__ uint4 ltwr[TWB > 0 ? TWB : 1];
+  cx<T>* ltw = reinterpret_cast<cx<T>*>(ltwr);
   __shared__ double gred[KindInfo<KIND>::ADJ ? 6 : 1][NGRAD];
   const int2 it = items[blockIdx.x];
   const PassArgs& a = args[it.x];
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.state);
   switch (a.n_line) {
-    case 64: pass_body<T, 64, 8, 8, KIND>(psi, a, it.y, lre, lim, gred); break;
-    case 128: pass_body<T, 128, 8, 4, KIND>(psi, a, it.y, lre, lim, gred); break;
-    case 256: pass_body<T, 256, 8, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
-    case 384: pass_body<T, 384, 12, 2, KIND>(psi, a, it.y, lre, lim, gred); break;
-    case 512: pass_body<T, 512, 8, 1, KIND>(psi, a, it.y, lre, lim, gred); break;
+    case 64: pass_body<T, 64, 8, 8, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
+    case 128: pass_body<T, 128, 8, 4, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
+    case 256: pass_body<T, 256, 8, 2, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
+    case 384: pass_body<T, 384, 12, 2, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
+    case 512: pass_body<T, 512, 8, 1, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
     default: break;
   }
 }
@@ -662,7 +686,7 @@ hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStrea
   cx<T>* p = reinterpret_cast<cx<T>*>(psi);
 #define SGP_CASE(NN, EE) \
   case NN:               \
-    if constexpr (plan_ok(NN, EE)) return pass_kind<T, NN, EE>(kind, p, a, st); \
+    if constexpr (plan_ok(NN, EE, (int)sizeof(T))) return pass_kind<T, NN, EE>(kind, p, a, st); \
     break;
   switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
 #undef SGP_CASE
@@ -674,7 +698,7 @@ hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, dou
   const cx<T>* p = reinterpret_cast<const cx<T>*>(psi);
 #define SGP_CASE(NN, EE) \
   case NN:               \
-    if constexpr (plan_ok(NN, EE)) return obs_kind<T, NN, EE>(kind, p, a, part, st); \
+    if constexpr (plan_ok(NN, EE, (int)sizeof(T))) return obs_kind<T, NN, EE>(kind, p, a, part, st); \
     break;
   switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
 #undef SGP_CASE

@@ -63,7 +63,7 @@ def lib():
     L.sgp_adjoint_segment.argtypes = [vp, vp, ctypes.c_long, vp, ctypes.c_size_t]
     L.sgp_adjoint_gradients.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     ip = ctypes.POINTER(ctypes.c_int)
-    L.sgp_plan_widths.argtypes = [ctypes.c_int, ip, ctypes.c_int]
+    L.sgp_plan_widths.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int]
     L.sgp_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sgp_get_plan.argtypes = [vp, ctypes.c_int, ip]
     L.sgp_autotune.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
@@ -86,10 +86,12 @@ def exported_symbols():
             "sgp_ensemble_last_error"]
 
 
-def plan_widths(n):
-    """Register plan widths E compiled for line length n (the default first)."""
+def plan_widths(n, dtype="complex64"):
+    """Register plan widths E compiled for line length n and element type (the
+    default first)."""
     out = (ctypes.c_int * 8)()
-    k = lib().sgp_plan_widths(int(n), out, 8)
+    code = SGP_C64 if str(dtype).replace("torch.", "") == "complex64" else SGP_C128
+    k = lib().sgp_plan_widths(int(n), code, out, 8)
     if k < 0:
         raise SgpError(f"unsupported line length {n}")
     return list(out[:k])

@@ -32,9 +32,9 @@ def run_plan(cfg, dtype, widths, steps, order=4, tau=1e-3):
     return got, psi0, s
 
 
-def plans_2d(nx, ny):
+def plans_2d(nx, ny, dtype="complex64"):
     from paper_2603_25282_amd.sgp import plan_widths
-    return [(ex, ey) for ex in plan_widths(nx) for ey in plan_widths(ny)]
+    return [(ex, ey) for ex in plan_widths(nx, dtype) for ey in plan_widths(ny, dtype)]
 
 
 @pytest.mark.parametrize("n", [16, 64, 128, 256])
@@ -42,7 +42,7 @@ def plans_2d(nx, ny):
 def test_every_plan_2d(n, dtype):
     cfg = I.with_(I.C2, shape=(n, n), L=8.0, name=f"plans-{n}")
     ref = None
-    for widths in plans_2d(n, n):
+    for widths in plans_2d(n, n, dtype):
         print(f"case plans 2D {n}^2 {dtype} widths={widths}", flush=True)
         got, psi0, _ = run_plan(cfg, dtype, widths, steps=6)
         if ref is None:
@@ -59,7 +59,7 @@ def test_every_plan_512_and_384(dtype):
     cfg = I.C2
     psi0 = I.initial_state(cfg)
     ref = oracle.evolve(psi0, cfg.L, cfg.params, cfg.order, cfg.tau, 2)
-    for widths in plans_2d(512, 512):
+    for widths in plans_2d(512, 512, dtype):
         print(f"case plans 512^2 {dtype} widths={widths}", flush=True)
         got, _, _ = run_plan(cfg, dtype, widths, steps=2, tau=cfg.tau)
         err = rel_l2(got, ref)
@@ -68,7 +68,7 @@ def test_every_plan_512_and_384(dtype):
     rc = I.with_(I.C2, shape=(64, 384), L=12.0, name="rect-384")
     psi0 = I.initial_state(rc)
     ref = oracle.evolve(psi0, rc.L, rc.params, 4, 1e-3, 4)
-    for widths in plans_2d(384, 64):
+    for widths in plans_2d(384, 64, dtype):
         print(f"case plans 64x384 {dtype} widths={widths}", flush=True)
         got, _, _ = run_plan(rc, dtype, widths, steps=4)
         err = rel_l2(got, ref)
