@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--workload", default="2d", choices=["2d", "3d"])
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pass-reps", type=int, default=200)
+    ap.add_argument("--pass-reps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the fwd+adjoint measurement (0 to skip)")
     ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
@@ -71,29 +71,43 @@ def main():
     # warmup (also captures the step graph)
     s.step(psi, a.warmup)
     torch.cuda.synchronize()
+    # the library runs on torch's current stream (the Solver was created on it), so
+    # these events bracket the timed region on the kernels' own stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     s.step(psi, a.steps)
+    ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    region_ms = ev0.elapsed_time(ev1)
     gps = npts * a.steps / elapsed
     finite = bool(torch.isfinite(torch.view_as_real(psi)).all().item())
 
-    # dominant kernel: average launch duration of each pass, HIP events on the
-    # library's stream, on a scratch copy of the state
+    # dominant kernel and its average launch duration in the timed region: each
+    # pass's share of a step from event pairs around its launches inside the pass
+    # sequence of a step (on a scratch copy of the state; the event overhead is
+    # common to all passes), times the event-timed step; back-to-back launches of
+    # one pass for reference
     scratch = psi.clone()
     passes = {"xpass": SGP_PASS_X, "ypass": SGP_PASS_Y} if cfg.dim == 2 else \
-        {"xpass": SGP_PASS_X, "ypass_fwd": SGP_PASS_Y, "zpass": SGP_PASS_Z}
+        {"xpass": SGP_PASS_X, "ypass_fwd": SGP_PASS_Y, "zpass": SGP_PASS_Z, "ypass_inv": SGP_PASS_YINV}
     # algorithmic bytes per grid point per launch: read + write 5 components, plus
-    # the (C - 1, S) propagator table (2 reals) on the pass that applies it
+    # the (C - 1, S) propagator table (2 reals per (x, y) wavevector) on the pass
+    # that applies it (3D: the z-pass reads it once per z-line, nz times smaller)
     table_b = 2 * esz // 2
     per_point = {"xpass": 2 * 5 * esz, "ypass": 2 * 5 * esz + (table_b if cfg.dim == 2 else 0),
-                 "ypass_fwd": 2 * 5 * esz, "zpass": 2 * 5 * esz}
-    launches_per_step = {"xpass": 3, "ypass": 3, "ypass_fwd": 6, "zpass": 3}
-    times = {}
+                 "ypass_fwd": 2 * 5 * esz, "zpass": 2 * 5 * esz, "ypass_inv": 2 * 5 * esz}
+    launches_per_step = {"xpass": 3, "ypass": 3, "ypass_fwd": 3, "zpass": 3, "ypass_inv": 3}
+    pair, iso = {}, {}
     for name, pk in passes.items():
-        s.time_pass(scratch, pk, 10)
-        times[name] = s.time_pass(scratch, pk, a.pass_reps)
+        s.time_pass(scratch, pk, 10, in_step=True)
+        pair[name] = s.time_pass(scratch, pk, a.pass_reps, in_step=True)
+        iso[name] = s.time_pass(scratch, pk, a.pass_reps)
+    step_ms = region_ms / a.steps
+    tot = sum(pair[k] * launches_per_step[k] for k in passes)
+    times = {k: step_ms * pair[k] / tot for k in passes}  # per launch, in the timed region
     dom = max(times, key=lambda k: times[k] * launches_per_step[k])
     bytes_launch = per_point[dom] * npts
     achieved = bytes_launch / (times[dom] * 1e-3) / 1e9
@@ -103,7 +117,7 @@ def main():
         try:
             tr = json.load(open(tpath))
             key = f"{cfg.name}:{a.dtype}:{dom}"
-            if key in tr and tr[key].get("source_hash") == source_hash():
+            if key in tr and tr[key].get("source_hash") == source_hash() and tr[key].get("plan") == plan:
                 traffic = tr[key]["bytes_per_launch"]
         except Exception:
             traffic = None
@@ -127,7 +141,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,
-                     "pass_ms": times},
+                     "pass_ms": times, "pass_ms_event_pairs": pair, "pass_ms_back_to_back": iso,
+                     "timing": "avg_launch_ms = event-timed step x the pass's share of a step (event pairs around "
+                               "its launches in step order) / its launches per step"},
     }
     # whole-step bandwidth of the bytes model (R round trips of the state per step)
     out["bytes_model"] = {"bytes_per_gp_step": sum(per_point[k] * launches_per_step[k] for k in passes),
@@ -159,14 +175,21 @@ def main():
                               "grad_finite": bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())}
 
     if not a.no_cpu_baseline:
+        # the FP64 oracle on the same workload from the same initial state, in chunks
+        # of steps continuing each other until about 15 s of CPU work (or the given
+        # number of steps)
         import oracle
-        k = a.cpu_sample_steps or (20 if cfg.dim == 2 else 1)
-        t0 = time.perf_counter()
-        oracle.evolve(psi0, cfg.L, cfg.params, cfg.order, cfg.tau, k)
-        tc = time.perf_counter() - t0
+        chunk = 10 if cfg.dim == 2 else 1
+        k, tc, u = 0, 0.0, psi0
+        while (a.cpu_sample_steps is None and tc < 15.0) or (a.cpu_sample_steps is not None and k < a.cpu_sample_steps):
+            t0 = time.perf_counter()
+            u = oracle.evolve(u, cfg.L, cfg.params, cfg.order, cfg.tau, chunk, t0=k * cfg.tau)
+            tc += time.perf_counter() - t0
+            k += chunk
         out["cpu_baseline"] = {"value": npts * k / tc, "unit": "gp-steps/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
-                               "sample": f"{k} TS4 steps of the same workload (FP64, own FFT) in {tc:.1f} s"}
+                               "sample": f"{k} TS{cfg.order} steps of the same workload from the same initial state "
+                                         f"(FP64, own FFT) in {tc:.1f} s"}
     if a.calib_copy_mb > 0:
         src = torch.empty(a.calib_copy_mb * 2 ** 20, dtype=torch.uint8, device=s.device)
         dst = torch.empty_like(src)
@@ -177,11 +200,13 @@ def main():
 
 
 def source_hash():
+    """Hash of the device-code sources (every kernel and what it includes; not the
+    host-side C ABI in sgp_api.hip): stored traffic counters apply only to them."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_25282_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
+        if f.endswith((".hip", ".hpp")) and f != "sgp_api.hip":
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 

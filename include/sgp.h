@@ -150,7 +150,12 @@ int sgp_set_time(sgp_ctx* ctx, double t);
  * (inverse FFT along x, nonlinear flow, forward FFT; the nonlinear flow of
  * Sec. 3.2); 1 = y-pass (2D: FFT along y, propagator, inverse FFT; 3D: forward
  * FFT along y); 2 = z-pass with the propagator (3D); 3 = inverse y-pass (3D).
- * Requires a built propagator.  Synchronous. */
+ * With pass | SGP_TIME_IN_STEP the passes of a substep run in step order (2D:
+ * y, X; 3D: y, z, inverse y, X) `reps` times and only the launches of the named
+ * pass are timed, each between its own pair of events (its data then comes from
+ * the previous pass, as inside sgp_step).  Requires a built propagator.
+ * Synchronous. */
+enum { SGP_TIME_IN_STEP = 256 };
 int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_ms);
 
 /* Register plans of the FFT line kernels.  Every pass along an axis of length n

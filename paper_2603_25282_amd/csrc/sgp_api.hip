@@ -395,20 +395,56 @@ int step_impl(sgp_ctx* c, void* psi, long nsteps) {
 // y (2D: with the propagator; 3D: forward y), 2 z-pass with the propagator (3D),
 // 3 inverse y-pass (3D).
 template <typename T>
+hipError_t launch_timed_pass(sgp_ctx* c, void* psi, int pass, bool first) {
+  // X-pass as inside a step: the clock from the device slots (set by the first launch)
+  if (pass == 0) return run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], first ? CLOCK_ARG : CLOCK_DEVICE, c->t);
+  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0);
+  if (pass == 2) return run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0);
+  return run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0);
+}
+
+// In-step timing: reps rounds of the passes of one linear + nonlinear substep in
+// step order (2D: y, X; 3D: y, z, inverse y, X), an event pair around every launch
+// of the timed pass; the average of those durations.
+template <typename T>
+int time_pass_in_step(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
+  const std::vector<int> order = c->g.dim == 2 ? std::vector<int>{1, 0} : std::vector<int>{1, 2, 3, 0};
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  bool first_x = true;
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    for (int p : order) {
+      if (p == pass) e = hipEventRecord(ev[2 * r], c->st);
+      if (e == hipSuccess) e = launch_timed_pass<T>(c, psi, p, p == 0 && first_x);
+      if (p == 0) first_x = false;
+      if (e == hipSuccess && p == pass) e = hipEventRecord(ev[2 * r + 1], c->st);
+      if (e != hipSuccess) break;
+    }
+  double total = 0.0;
+  if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+    total += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(c, e, "pass timing");
+  *avg_ms = total / reps;
+  return SGP_OK;
+}
+
+template <typename T>
 int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
+  if (pass & SGP_TIME_IN_STEP) return time_pass_in_step<T>(c, psi, pass & ~SGP_TIME_IN_STEP, reps, avg_ms);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return hip_fail(c, e, "event create");
   e = hipEventCreate(&e1);
   if (e != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, e, "event create"); }
   e = hipEventRecord(e0, c->st);
-  for (int i = 0; i < reps && e == hipSuccess; ++i) {
-    // X-pass as inside a step: the clock from the device slots (set by the first launch)
-    if (pass == 0) e = run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], i == 0 ? CLOCK_ARG : CLOCK_DEVICE, c->t);
-    else if (pass == 1) e = run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0);
-    else if (pass == 2) e = run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0);
-    else e = run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0);
-  }
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_timed_pass<T>(c, psi, pass, i == 0);
   if (e == hipSuccess) e = hipEventRecord(e1, c->st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
@@ -765,7 +801,9 @@ int sgp_set_time(sgp_ctx* c, double t) {
 
 int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   if (!c || !psi || !avg_ms || reps < 1) return fail(c, SGP_ERR_ARG, "bad argument");
-  if (pass < 0 || pass > 3 || (c->g.dim == 2 && pass > 1)) return fail(c, SGP_ERR_ARG, "no such pass");
+  const int kind = pass & ~SGP_TIME_IN_STEP;
+  if (kind < 0 || kind > 3 || (c->g.dim == 2 && kind > 1) || (pass & ~(SGP_TIME_IN_STEP | 3)))
+    return fail(c, SGP_ERR_ARG, "no such pass");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
   return c->dtype == SGP_C64 ? time_pass_impl<float>(c, psi, pass, reps, avg_ms)

@@ -21,6 +21,7 @@ SGP_C64, SGP_C128 = 0, 1
 SGP_TS2, SGP_TS4 = 2, 4
 SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
 SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
+SGP_TIME_IN_STEP = 256
 
 
 class SgpError(RuntimeError):
@@ -179,9 +180,11 @@ class Solver:
         _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
         return np.array(out[:])
 
-    def time_pass(self, psi, pass_kind, reps):
+    def time_pass(self, psi, pass_kind, reps, in_step=False):
         """Average milliseconds of one pass (0 X, 1 Y, 2 Z, 3 inverse Y) over reps
-        back-to-back launches, timed with HIP events on the library's stream."""
+        launches, timed with HIP events on the library's stream: back to back, or
+        (in_step) inside the pass sequence of a step, one event pair per launch."""
+        pass_kind = int(pass_kind) | (SGP_TIME_IN_STEP if in_step else 0)
         ms = ctypes.c_double()
         _check(lib().sgp_time_pass(self._ctx, self._psi_ptr(psi), int(pass_kind), int(reps), ctypes.byref(ms)),
                self._ctx)
