@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
@@ -36,6 +38,8 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the fwd+adjoint measurement (0 to skip)")
     ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
+    ap.add_argument("--unfused-steps", type=int, default=20,
+                    help="steps of the plain unfused FP64 comparison step (0 to skip; 2D only)")
     ap.add_argument("--plan", default="auto",
                     help='register plans: "auto" (autotuned before the timed region), "default", or widths "ex,ey[,ez]"')
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -53,7 +57,7 @@ def main():
     import torch
 
     from paper_2603_25282_amd import inputs as I
-    from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, Solver
+    from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, Solver
 
     cfg = I.C2 if a.workload == "2d" else I.C3
     esz = 8 if a.dtype == "complex64" else 16
@@ -174,6 +178,24 @@ def main():
                               "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj,
                               "grad_finite": bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())}
 
+    if a.unfused_steps > 0 and cfg.dim == 2:
+        # the plain unfused FP64 GPU step (PyTorch operations) on the same workload
+        ub = UnfusedFP64(cfg.shape, cfg.L, cfg.params, s.device)
+        u = torch.from_numpy(psi0).to(s.device)
+        u = ub.evolve(u, cfg.order, cfg.tau, 2)  # warmup (tables, FFT plans)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = ub.evolve(u, cfg.order, cfg.tau, a.unfused_steps, t0=2 * cfg.tau)
+        torch.cuda.synchronize()
+        tu = time.perf_counter() - t0
+        out["baseline_unfused_fp64"] = {
+            "value": npts * a.unfused_steps / tu, "unit": "gp-steps/s", "ms_per_step": tu * 1e3 / a.unfused_steps,
+            "steps": a.unfused_steps, "speedup_of_value": gps / (npts * a.unfused_steps / tu),
+            "finite": bool(torch.isfinite(torch.view_as_real(u)).all().item()),
+            "what": "plain FP64 step in PyTorch-ROCm operations (hipFFT over the grid, batched 5x5 products, "
+                    "elementwise nonlinear flow), same scheme and workload"}
+        del ub, u
+
     if not a.no_cpu_baseline:
         # the FP64 oracle on the same workload from the same initial state, in chunks
         # of steps continuing each other until about 15 s of CPU work (or the given
@@ -197,6 +219,121 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = src.numel()
     print(json.dumps(out), flush=True)
+
+
+class UnfusedFP64:
+    """Plain, unfused FP64 GPU split step (2D) in PyTorch-ROCm operations, as the
+    comparison point for the fused path: every stage is its own library call over
+    the whole state (hipFFT through torch.fft over the grid per component, one
+    batched 5x5 product per wavevector with the propagator exp(-i d |nu|^2/2)
+    exp(i d Q) (Sec. 3.1) built by matrix exponentials, and the nonlinear flow of
+    Sec. 3.2 as elementwise operations, the spin rotation exp(-i c1 d F.f) through
+    the eigenprojectors of the spin-2 matrix F.f/|F| (eigenvalues -2..2)).  Same
+    composition as the library: TS2/TS4 with merged nonlinear substeps, trap at
+    R(Omega s) x with s the linear-substep clock.  State: (5, ny, nx) complex128."""
+
+    def __init__(self, shape, L, params, device):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.dev = device
+        self.ny, self.nx = shape
+        self.L = float(L)
+        self.c0, self.c1, self.c2, self.Om, self.ga, gx, gy, _ = [float(v) for v in params]
+        self.g2 = (gx * gx, gy * gy)
+        h6 = np.sqrt(6.0) / 2.0
+        fx = np.zeros((5, 5), complex)
+        fy = np.zeros((5, 5), complex)
+        for i, w in enumerate([1.0, h6, h6, 1.0]):
+            fx[i, i + 1] = fx[i + 1, i] = w
+            fy[i, i + 1], fy[i + 1, i] = -1j * w, 1j * w
+        fz = np.diag([2.0, 1.0, 0.0, -1.0, -2.0]).astype(complex)
+        self.f = [torch.tensor(m, dtype=torch.complex128, device=device) for m in (fx, fy, fz)]
+        # monomial coefficients of the Lagrange basis on the nodes m = 2..-2:
+        # exp(-i t N) = sum_m exp(-i t m) prod_{m' != m} (N - m') / (m - m')
+        nodes = [2.0, 1.0, 0.0, -1.0, -2.0]
+        lag = np.zeros((5, 5))
+        for k, m in enumerate(nodes):
+            poly = np.poly1d([1.0])
+            for mp in nodes:
+                if mp != m:
+                    poly = poly * np.poly1d([1.0, -mp]) / (m - mp)
+            lag[k, :] = poly.coeffs[::-1]  # coefficient of N^j
+        self.nodes = torch.tensor(nodes, dtype=torch.float64, device=device)
+        self.lag = torch.tensor(lag, dtype=torch.complex128, device=device)
+        x = -self.L + 2.0 * self.L / self.nx * torch.arange(self.nx, dtype=torch.float64, device=device)
+        y = -self.L + 2.0 * self.L / self.ny * torch.arange(self.ny, dtype=torch.float64, device=device)
+        self.Y, self.X = torch.meshgrid(y, x, indexing="ij")
+        p = torch.fft.fftfreq(self.nx, d=1.0 / self.nx, dtype=torch.float64, device=device)
+        q = torch.fft.fftfreq(self.ny, d=1.0 / self.ny, dtype=torch.float64, device=device)
+        self.nuq, self.nup = torch.meshgrid(np.pi * q / self.L, np.pi * p / self.L, indexing="ij")
+        self.tables = {}
+
+    def table(self, d):
+        """exp(-i d |nu|^2/2) exp(i d Q) per wavevector, (ny nx, 5, 5)."""
+        torch = self.torch
+        if d not in self.tables:
+            a = -self.nuq - 1j * self.nup
+            fx, fy, fz = self.f
+            Q = (self.ga * a.real)[..., None, None] * fx - (self.ga * a.imag)[..., None, None] * fy - self.Om * fz
+            E = torch.linalg.matrix_exp(1j * d * Q.reshape(-1, 5, 5))
+            kin = torch.exp(-0.5j * d * (self.nup ** 2 + self.nuq ** 2)).reshape(-1, 1, 1)
+            self.tables[d] = (kin * E).contiguous()
+        return self.tables[d]
+
+    def linear(self, psi, d):
+        torch = self.torch
+        F = torch.fft.fft2(psi, norm="forward")
+        v = F.reshape(5, -1).transpose(0, 1).contiguous().unsqueeze(-1)
+        v = torch.matmul(self.table(d), v)
+        F = v.squeeze(-1).transpose(0, 1).contiguous().reshape(5, self.ny, self.nx)
+        return torch.fft.ifft2(F, norm="forward")
+
+    def nonlinear(self, psi, d, s):
+        torch = self.torch
+        c, sn = np.cos(self.Om * s), np.sin(self.Om * s)
+        Xr, Yr = c * self.X + sn * self.Y, -sn * self.X + c * self.Y
+        V = 0.5 * (self.g2[0] * Xr * Xr + self.g2[1] * Yr * Yr)
+        rho = (psi.real ** 2 + psi.imag ** 2).sum(0)
+        fx, fy, fz = self.f
+        Fv = [torch.einsum("ipq,ij,jpq->pq", psi.conj(), f, psi).real for f in (fx, fy, fz)]
+        A00 = (2.0 * (psi[0] * psi[4] - psi[1] * psi[3]) + psi[2] * psi[2]) / np.sqrt(5.0)
+        Apsi = torch.stack([psi[4].conj(), -psi[3].conj(), psi[2].conj(), -psi[1].conj(), psi[0].conj()]) / np.sqrt(5.0)
+        S = torch.sqrt(torch.clamp((rho / 5.0) ** 2 - (A00.real ** 2 + A00.imag ** 2) / 5.0, min=0.0))
+        x = self.c2 * d * S
+        snc = torch.where(x == 0, torch.ones_like(x), torch.sin(x) / torch.where(x == 0, torch.ones_like(x), x))
+        b = torch.cos(x) * psi + 1j * (self.c2 * d * snc) * (rho / 5.0 * psi - A00 * Apsi)
+        Fa = torch.sqrt(Fv[0] ** 2 + Fv[1] ** 2 + Fv[2] ** 2)
+        safe = torch.where(Fa == 0, torch.ones_like(Fa), Fa)
+        N = (Fv[0] / safe)[..., None, None] * fx + (Fv[1] / safe)[..., None, None] * fy + (Fv[2] / safe)[..., None, None] * fz
+        N = N.reshape(-1, 5, 5)
+        t = (self.c1 * d * Fa).reshape(-1)
+        coef = torch.matmul(torch.exp(-1j * t[:, None] * self.nodes[None, :]), self.lag)  # (P, 5): of N^0..N^4
+        eye = torch.eye(5, dtype=torch.complex128, device=self.dev).expand_as(N)
+        N2 = torch.matmul(N, N)
+        U = (coef[:, 0, None, None] * eye + coef[:, 1, None, None] * N + coef[:, 2, None, None] * N2 +
+             coef[:, 3, None, None] * torch.matmul(N2, N) + coef[:, 4, None, None] * torch.matmul(N2, N2))
+        bv = b.reshape(5, -1).transpose(0, 1).contiguous().unsqueeze(-1)
+        out = torch.matmul(U, bv).squeeze(-1).transpose(0, 1).reshape(5, self.ny, self.nx)
+        return torch.exp(-1j * d * (V + (self.c0 + self.c2 / 5.0) * rho)) * out
+
+    def evolve(self, psi, order, tau, nsteps, t0=0.0):
+        if order == 2:
+            a, b = [0.5], [1.0]
+        else:
+            cb = 2.0 ** (1.0 / 3.0)
+            a1, a2 = 1.0 / (2.0 * (2.0 - cb)), (1.0 - cb) / (2.0 * (2.0 - cb))
+            b1, b2 = 1.0 / (2.0 - cb), -cb / (2.0 - cb)
+            a, b = [a1, a2, a2], [b1, b2, b1]
+        s = t0
+        for n in range(nsteps):
+            for k in range(len(b)):
+                # merged nonlinear substeps: a_first of a step joins a_last of the previous one
+                dn = a[k] * tau if k > 0 else (a[0] * tau if n == 0 else 2.0 * a[0] * tau)
+                psi = self.nonlinear(psi, dn, s)
+                psi = self.linear(psi, b[k] * tau)
+                s += b[k] * tau
+        return self.nonlinear(psi, a[0] * tau, s)
 
 
 def source_hash():

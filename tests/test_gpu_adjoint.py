@@ -132,3 +132,26 @@ def test_differentiation_workload_full(dtype):
         assert eJ <= 1e-10 and eg <= 1e-10 and np.all(ed <= 1e-8)
     else:
         assert eJ <= 1e-4 and eg <= 1e-4 and np.all(ed <= 1e-3)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_3d_adjoint_matches_oracle_adjoint(dtype, order):
+    # 3D adjoint passes (X adjoint; y forward, z adjoint with the propagator partials,
+    # y inverse) on an anisotropic rotating trap, with checkpoints
+    params = (40.0, -1.5, 2.0, 0.6, 0.8, 1.0, 1.3, 2.0)
+    L, shape = 5.0, (16, 16, 32)
+    from paper_2603_25282_amd import inputs as II
+    cfg = II.with_(II.C3, shape=shape, L=L, params=params, name="adj3d")
+    psi = II.initial_state(cfg)
+    w = np.random.default_rng(9).standard_normal(psi.shape) + 1j * np.random.default_rng(10).standard_normal(psi.shape)
+    tau, n = 3e-3, 5
+    print(f"case 3D adjoint {shape} {dtype} TS{order}", flush=True)
+    g_ref, d_ref = oracle.adjoint(psi, w, L, params, order, tau, n, K=2)
+    g, d, _ = gpu_adjoint(psi, w, L, params, order, tau, n, K=2, dtype=dtype)
+    eg = rel_l2(g, g_ref)
+    ed = np.abs(d - d_ref) / np.maximum(1.0, np.abs(d_ref))
+    print("state grad rel l2", eg, "param grads", d, "oracle", d_ref, "rel", ed)
+    tol = 1e-11 if dtype == "complex128" else 5e-5
+    assert eg <= tol
+    assert np.all(ed <= (1e-10 if dtype == "complex128" else 2e-4))
