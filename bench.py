@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the fwd+adjoint measurement (0 to skip)")
     ap.add_argument("--K", type=int, default=50, help="checkpoint interval of the fwd+adjoint measurement")
+    ap.add_argument("--lab-steps", type=int, default=50,
+                    help="steps of the lab-frame Algorithm 1 mode (rotation mapping around every linear substep; 0 to skip)")
     ap.add_argument("--unfused-steps", type=int, default=20,
                     help="steps of the plain unfused FP64 comparison step (0 to skip; 2D only)")
     ap.add_argument("--plan", default="auto",
@@ -177,6 +179,25 @@ def main():
         out["fwd_adjoint"] = {"metric": "5-comp grid-point-steps/s fwd+adjoint", "value": npts * n_adj / ta,
                               "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj,
                               "grad_finite": bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())}
+
+    if a.lab_steps > 0:
+        # Algorithm 1 run literally (lab frame): the like-for-like form of the paper's
+        # own step, with the rotation mapping before and after every linear substep
+        sl = Solver(cfg.shape, cfg.L, cfg.params, dtype=a.dtype)
+        sl.set_frame("lab")
+        sl.build_propagator(cfg.tau, cfg.order)
+        sl.set_plan(plan)
+        pl = torch.from_numpy(Solver.to_device_layout(psi0)).to(sl.torch_dtype).to(sl.device).contiguous()
+        sl.step(pl, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sl.step(pl, a.lab_steps)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        out["lab_frame_algorithm1"] = {
+            "value": npts * a.lab_steps / tl, "unit": "gp-steps/s", "ms_per_step": tl * 1e3 / a.lab_steps,
+            "steps": a.lab_steps, "finite": bool(torch.isfinite(torch.view_as_real(pl)).all().item())}
+        del sl, pl
 
     if a.unfused_steps > 0 and cfg.dim == 2:
         # the plain unfused FP64 GPU step (PyTorch operations) on the same workload

@@ -190,8 +190,26 @@ int sgp_autotune(sgp_ctx* ctx, void* psi_dev, int steps, int elems_out[3], doubl
 
 /* Options.  SGP_OPT_GRAPH (default 1): replay the periodic part of sgp_step()
  * from a captured HIP graph (value 0 launches every kernel individually). */
-enum { SGP_OPT_GRAPH = 1, SGP_OPT_BATCHED = 2 };
+enum { SGP_OPT_GRAPH = 1, SGP_OPT_BATCHED = 2, SGP_OPT_FRAME = 3 };
+/* SGP_OPT_FRAME: SGP_FRAME_ROTATING (default) evolves Phi in the rotating frame
+ * (trap at R(Omega s) x, merged nonlinear substeps, graph replay); SGP_FRAME_LAB runs
+ * Algorithm 1 literally on the lab-frame Psi: nonlinear substeps with the trap at x
+ * (not merged) and the rotation mapping before and its inverse after every linear
+ * substep (Sec. 3.3).  In the lab frame sgp_observables evaluates the trap at x, and
+ * sgp_step_store / sgp_adjoint_segment return SGP_ERR_STATE. */
+enum { SGP_FRAME_ROTATING = 0, SGP_FRAME_LAB = 1 };
 int sgp_set_option(sgp_ctx* ctx, int option, long value);
+
+/* Rotation mapping (Sec. 3.1, eqs. RSDA1/RSDA2) in place on a physical-space state
+ * [nz][ny][nx][5]: direction +1 maps the lab-frame Psi to Phi = M_t Psi,
+ * phi_l(x) = exp(-i l Omega t) psi_l(R(Omega t) x); direction -1 maps back, Psi =
+ * M_t^{-1} Phi.  The rotation (about z in 3D) is three shears
+ * exp(a y d_x) exp(b x d_y) exp(a y d_x), a = +-tan(Omega t/2), b = -+sin(Omega t),
+ * each a transform along one axis, a phase per Fourier coefficient and the
+ * inverse transform (spectrally exact for band-limited data).  SGP_ERR_ARG when
+ * |cos(Omega t/2)| < 1e-6 (the shear factorisation degenerates at angle pi).
+ * Needs the workspace (twiddles); asynchronous on the context stream. */
+int sgp_rotation_map(sgp_ctx* ctx, void* psi_dev, double t, int direction);
 
 /* Release the context (not the caller's workspace or state). */
 void sgp_destroy(sgp_ctx* ctx);
@@ -203,9 +221,9 @@ const char* sgp_last_error(const sgp_ctx* ctx);
 /* ---- Ensembles of 2D grids -------------------------------------------------
  * Many independent 2D instances (square grids with N in {64, 128, 256, 384, 512},
  * each with its own domain and parameters, same element type and scheme) advanced
- * together: every pass type of a step is one batched launch over the work list of
- * all instances' line tiles, and the periodic part of a step is replayed from one
- * HIP graph.  Each instance evolves exactly as with its own context (same kernels
+ * together: every pass type of a step is one batched launch (per register plan
+ * width in use) over the work list of the instances' line tiles, and the periodic
+ * part of a step is replayed from one HIP graph.  Each instance evolves exactly as with its own context (same kernels
  * per line; results are bitwise identical). */
 typedef struct sgp_ensemble sgp_ensemble;
 
@@ -222,6 +240,23 @@ int sgp_ensemble_step(sgp_ensemble* ens, void* const* psi_devs, long nsteps);
 /* SGP_OPT_GRAPH (default 1) as for contexts; SGP_OPT_BATCHED (default 1): 0 runs
  * every instance with its own launches (the unbatched reference). */
 int sgp_ensemble_set_option(sgp_ensemble* ens, int option, long value);
+/* Register plans of an ensemble (see sgp_set_plan): the width used along `axis`
+ * (0 = x-lines, 1 = y-lines) by every instance of size n x n.  Batched kernels
+ * run the 320-thread geometry, so the widths available are those of
+ * sgp_plan_widths(n, dtype) with n/E <= 64 (all but E = 4 at n = 512).  Each pass
+ * type of a step is one batched launch per plan width in use.
+ * sgp_ensemble_set_plan: elems = 0 restores the default; SGP_ERR_ARG if the width
+ *   is not available or no instance has size n.  Drops the captured step graph.
+ * sgp_ensemble_get_plan: the width of the first instance of size n.
+ * sgp_ensemble_autotune: for each instance size and axis in turn (the others at
+ *   their current best), times `steps` ensemble steps per candidate width (after
+ *   one untimed call of `steps` steps) and keeps the fastest; psi_devs are
+ *   advanced by every step (pass scratch copies); the ensemble time is restored;
+ *   ms_per_step (if not NULL) receives the fastest time per step. */
+int sgp_ensemble_set_plan(sgp_ensemble* ens, int n, int axis, int elems);
+int sgp_ensemble_get_plan(const sgp_ensemble* ens, int n, int axis, int* elems);
+int sgp_ensemble_autotune(sgp_ensemble* ens, void* const* psi_devs, int steps, double* ms_per_step);
+
 void sgp_ensemble_destroy(sgp_ensemble* ens);
 const char* sgp_ensemble_last_error(const sgp_ensemble* ens);
 

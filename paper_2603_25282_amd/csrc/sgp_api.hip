@@ -90,6 +90,8 @@ struct sgp_ctx {
 
   // register plan width E of the passes along each axis
   int plan_e[3] = {0, 0, 0};
+  // 0: evolve Phi in the rotating frame (default); 1: Algorithm 1 literally (lab frame)
+  int frame = 0;
 
   int scheme = 0;
   double tau = 0.0;
@@ -557,7 +559,7 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
     } else {
       column_geometry(c, axis, a);
     }
-    a.s_arg = c->t;
+    a.s_arg = c->frame == SGP_FRAME_LAB ? 0.0 : c->t;  // lab frame: the trap at x
     const int kind = axis == 0 ? OBS_X : (axis == 1 ? OBS_Y : OBS_Z);
     hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], c->elems(axis), part, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "observables launch");
@@ -582,6 +584,82 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
   out[2] = hd * tot[0][1];
   out[3] = hd * lz;
   out[1] = hd * (ekin + tot[0][2] + tot[0][3] - c->p.gamma * soc) - c->p.Omega * out[3];
+  return SGP_OK;
+}
+
+// Rotation mapping of Sec. 3.1 by the three shears of eqs. RSDA1/RSDA2, each a
+// transform along one axis, a phase exp(i nu a w) per coefficient and the inverse
+// transform: dir = +1 gives Phi = M_t Psi, phi_l = exp(-i l Omega t) psi_l(R(t) x);
+// dir = -1 gives Psi = M_t^{-1} Phi.
+template <typename T>
+hipError_t run_shear(sgp_ctx* c, void* psi, int kind, double coef, bool cph, double cphase) {
+  PassArgs a = base_args(c);
+  if (kind == X_SHEAR) {
+    a.tw_fwd = c->at(c->off_tw[0][0]);
+    a.tw_inv = c->at(c->off_tw[0][1]);
+  } else {
+    column_geometry(c, 1, a);
+  }
+  a.shear = coef;
+  a.cphase_on = cph ? 1 : 0;
+  a.cphase = cphase;
+  const int axis = kind == X_SHEAR ? 0 : 1;
+  return launch_pass<T>(kind, psi, a, c->g.n[axis], c->elems(axis), c->st);
+}
+
+template <typename T>
+int rotation_map_impl(sgp_ctx* c, void* psi, double t, int dir) {
+  const double th = c->p.Omega * t;
+  if (std::fabs(std::cos(0.5 * th)) < 1e-6)
+    return fail(c, SGP_ERR_ARG, "rotation angle Omega t too close to an odd multiple of pi for the shears");
+  const double a = (dir > 0 ? 1.0 : -1.0) * std::tan(0.5 * th);
+  const double b = (dir > 0 ? -1.0 : 1.0) * std::sin(th);
+  hipError_t e = run_shear<T>(c, psi, X_SHEAR, a, false, 0.0);
+  if (e == hipSuccess) e = run_shear<T>(c, psi, C_SHEAR, b, false, 0.0);
+  if (e == hipSuccess) e = run_shear<T>(c, psi, X_SHEAR, a, true, (dir > 0 ? -1.0 : 1.0) * th);
+  if (e != hipSuccess) return hip_fail(c, e, "rotation map launch");
+  return SGP_OK;
+}
+
+// Algorithm 1 literally (lab frame): per step the nonlinear substeps with the trap
+// at x (not merged), and around every linear substep of length d starting at clock s
+// the mapping M_s before and M_{s+d}^{-1} after; the linear substep itself is the
+// same propagator pass, between bare transforms along x.
+template <typename T>
+int lab_step_impl(sgp_ctx* c, void* psi, long nsteps) {
+  std::vector<double> A, B;
+  std::vector<int> tab;
+  if (c->scheme == SGP_TS2) {
+    A = {0.5, 0.5};
+    B = {1.0, 0.0};
+    tab = {0, 0};
+  } else {
+    TS4 k;
+    A = {k.a1, k.a2, k.a2, k.a1};
+    B = {k.b1, k.b2, k.b1, 0.0};
+    tab = {0, 1, 0, 0};
+  }
+  const double t0 = c->t, tau = c->tau;
+  for (long n = 0; n < nsteps; ++n) {
+    double s = t0 + (double)n * tau;
+    for (size_t j = 0; j < A.size(); ++j) {
+      hipError_t e = hipSuccess;
+      if (A[j] != 0.0) e = run_xpass<T>(c, c->st, X_NLONLY, psi, A[j] * tau, CLOCK_ARG, 0.0);
+      if (e != hipSuccess) return hip_fail(c, e, "nonlinear pass launch");
+      if (B[j] == 0.0) continue;
+      const double d = B[j] * tau;
+      int rc = rotation_map_impl<T>(c, psi, s, +1);
+      if (rc != SGP_OK) return rc;
+      e = run_xpass<T>(c, c->st, X_FWD, psi, 0.0, CLOCK_ARG, 0.0);
+      if (e == hipSuccess) e = run_linear<T>(c, c->st, psi, tab[j], d);
+      if (e == hipSuccess) e = run_xpass<T>(c, c->st, X_INV, psi, 0.0, CLOCK_ARG, 0.0);
+      if (e != hipSuccess) return hip_fail(c, e, "linear pass launch");
+      rc = rotation_map_impl<T>(c, psi, s + d, -1);
+      if (rc != SGP_OK) return rc;
+      s += d;
+    }
+  }
+  c->t = t0 + (double)nsteps * tau;
   return SGP_OK;
 }
 
@@ -778,7 +856,18 @@ int sgp_step(sgp_ctx* c, void* psi, long nsteps) {
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
   if (nsteps == 0) return SGP_OK;
+  if (c->frame == SGP_FRAME_LAB)
+    return c->dtype == SGP_C64 ? lab_step_impl<float>(c, psi, nsteps) : lab_step_impl<double>(c, psi, nsteps);
   return c->dtype == SGP_C64 ? step_impl<float>(c, psi, nsteps) : step_impl<double>(c, psi, nsteps);
+}
+
+int sgp_rotation_map(sgp_ctx* c, void* psi, double t, int direction) {
+  if (!c || !psi) return fail(c, SGP_ERR_ARG, "null argument");
+  if (direction != 1 && direction != -1) return fail(c, SGP_ERR_ARG, "direction must be +1 or -1");
+  if (!std::isfinite(t)) return fail(c, SGP_ERR_ARG, "non-finite time");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  return c->dtype == SGP_C64 ? rotation_map_impl<float>(c, psi, t, direction)
+                             : rotation_map_impl<double>(c, psi, t, direction);
 }
 
 int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
@@ -819,6 +908,7 @@ int sgp_store_size(const sgp_ctx* c, long nsteps, size_t* bytes) {
 }
 
 int sgp_step_store(sgp_ctx* c, void* psi, long nsteps, void* store, size_t store_bytes) {
+  if (c && c->frame == SGP_FRAME_LAB) return fail(c, SGP_ERR_STATE, "the adjoint runs in the rotating frame only");
   if (!c || !psi || !store) return fail(c, SGP_ERR_ARG, "null argument");
   if (nsteps < 1) return fail(c, SGP_ERR_ARG, "nsteps must be >= 1");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
@@ -831,6 +921,7 @@ int sgp_step_store(sgp_ctx* c, void* psi, long nsteps, void* store, size_t store
 }
 
 int sgp_adjoint_segment(sgp_ctx* c, void* lam, long nsteps, const void* store, size_t store_bytes) {
+  if (c && c->frame == SGP_FRAME_LAB) return fail(c, SGP_ERR_STATE, "the adjoint runs in the rotating frame only");
   if (!c || !lam || !store) return fail(c, SGP_ERR_ARG, "null argument");
   if (nsteps < 1) return fail(c, SGP_ERR_ARG, "nsteps must be >= 1");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
@@ -897,6 +988,12 @@ int sgp_set_option(sgp_ctx* c, int option, long value) {
     if (!c->use_graph) drop_graph(c);
     return SGP_OK;
   }
+  if (option == SGP_OPT_FRAME) {
+    if (value != SGP_FRAME_ROTATING && value != SGP_FRAME_LAB) return fail(c, SGP_ERR_ARG, "unknown frame");
+    c->frame = (int)value;
+    drop_graph(c);
+    return SGP_OK;
+  }
   return fail(c, SGP_ERR_ARG, "unknown option");
 }
 
@@ -924,8 +1021,11 @@ struct sgp_ensemble {
   std::vector<sgp_ctx*> ctx;
   std::vector<size_t> ws_off;
   size_t total = 0;
-  size_t off_items_x = 0, off_items_y = 0, off_args = 0;
-  long nitems_x = 0, nitems_y = 0;
+  // work lists per axis (0: x-lines, 1: columns), grouped by plan width: one
+  // batched launch per group
+  struct Group { int e; long off; long n; };
+  size_t off_items[2] = {0, 0}, off_args = 0;
+  std::vector<Group> groups[2];
   char* ws = nullptr;
   int nslots = 0;  // PassArgs slots (per instance): see ens_slots()
   std::vector<void*> psis;
@@ -1012,8 +1112,45 @@ hipError_t ens_launch(sgp_ensemble* e, hipStream_t st, int slot) {
   const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
   const bool xl = slot <= ES_XLAST;
   const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
-  return launch_pass_batched<T>(kind, e->ws + (xl ? e->off_items_x : e->off_items_y), args,
-                                xl ? e->nitems_x : e->nitems_y, st);
+  const int ax = xl ? 0 : 1;
+  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
+  for (const auto& g : e->groups[ax]) {
+    hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args, g.n, st);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
+}
+
+// Tiles of an instance along one axis for plan width w (2D: N lines either way).
+long ens_tiles(int N, int w) {
+  const int W = lines_per_block(N, w);
+  return (N + W - 1) / W;
+}
+
+// Rebuild and upload the work lists for the instances' current plans.
+hipError_t ens_build_items(sgp_ensemble* e) {
+  for (int ax = 0; ax < 2; ++ax) {
+    std::vector<int> widths;
+    for (auto* c : e->ctx)
+      if (std::find(widths.begin(), widths.end(), c->plan_e[ax]) == widths.end()) widths.push_back(c->plan_e[ax]);
+    std::sort(widths.begin(), widths.end());
+    std::vector<int2> items;
+    e->groups[ax].clear();
+    for (int w : widths) {
+      sgp_ensemble::Group g{w, (long)items.size(), 0};
+      for (int i = 0; i < e->n; ++i) {
+        if (e->ctx[i]->plan_e[ax] != w) continue;
+        const long nt = ens_tiles(e->ctx[i]->g.n[0], w);
+        for (long t = 0; t < nt; ++t) items.push_back(make_int2(i, (int)t));
+      }
+      g.n = (long)items.size() - g.off;
+      e->groups[ax].push_back(g);
+    }
+    hipError_t r = hipMemcpyAsync(e->ws + e->off_items[ax], items.data(), sizeof(int2) * items.size(),
+                                  hipMemcpyHostToDevice, e->st);
+    if (r != hipSuccess) return r;
+  }
+  return hipStreamSynchronize(e->st);
 }
 
 // Slots of one body step (after a merged nonlinear substep, ending with the next one)
@@ -1081,7 +1218,6 @@ int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* par
   e->dtype = dtype;
   e->st = (hipStream_t)hip_stream;
   size_t off = 0;
-  std::vector<int2> items_x, items_y;
   for (int i = 0; i < n_inst; ++i) {
     if (grids[i].dim != 2 || grids[i].n[0] != grids[i].n[1] ||
         (grids[i].n[0] != 64 && grids[i].n[0] != 128 && grids[i].n[0] != 256 && grids[i].n[0] != 384 &&
@@ -1100,20 +1236,19 @@ int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* par
     e->ctx.push_back(c);
     e->ws_off.push_back(off);
     off += align256(c->total);
-    const int N = grids[i].n[0];
-    const int W = batched_lines_per_block(N);
-    const int ntiles = (N + W - 1) / W;  // x-lines: ny lines; columns: nx columns (nouter = 1)
-    for (int tIdx = 0; tIdx < ntiles; ++tIdx) {
-      items_x.push_back(make_int2(i, tIdx));
-      items_y.push_back(make_int2(i, tIdx));
-    }
   }
-  e->nitems_x = (long)items_x.size();
-  e->nitems_y = (long)items_y.size();
-  e->off_items_x = off;
-  off += align256(sizeof(int2) * items_x.size());
-  e->off_items_y = off;
-  off += align256(sizeof(int2) * items_y.size());
+  // work-list room: the most tiles any batched plan gives each instance
+  long cap = 0;
+  for (auto* c : e->ctx) {
+    long most = 0;
+    for (int w : kPlanElems)
+      if (batched_plan_ok(c->g.n[0], w, (int)c->esize)) most = std::max(most, ens_tiles(c->g.n[0], w));
+    cap += most;
+  }
+  for (int ax = 0; ax < 2; ++ax) {
+    e->off_items[ax] = off;
+    off += align256(sizeof(int2) * cap);
+  }
   e->off_args = off;
   off += align256(sizeof(PassArgs) * ES_N * n_inst);
   e->total = off;
@@ -1137,18 +1272,7 @@ int sgp_ensemble_set_workspace(sgp_ensemble* e, void* dev_ptr, size_t bytes) {
     int rc = sgp_set_workspace(e->ctx[i], e->ws + e->ws_off[i], e->ctx[i]->total);
     if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);
   }
-  std::vector<int2> items;
-  for (int i = 0; i < e->n; ++i) {
-    const int N = e->ctx[i]->g.n[0];
-    const int W = batched_lines_per_block(N);
-    for (int tIdx = 0; tIdx < (N + W - 1) / W; ++tIdx) items.push_back(make_int2(i, tIdx));
-  }
-  hipError_t r = hipMemcpyAsync(e->ws + e->off_items_x, items.data(), sizeof(int2) * items.size(),
-                                hipMemcpyHostToDevice, e->st);
-  if (r == hipSuccess)
-    r = hipMemcpyAsync(e->ws + e->off_items_y, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice,
-                       e->st);
-  if (r == hipSuccess) r = hipStreamSynchronize(e->st);
+  hipError_t r = ens_build_items(e);
   if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "work list upload");
   e->args_ok = false;
   drop_egraph(e);
@@ -1196,6 +1320,96 @@ int sgp_ensemble_step(sgp_ensemble* e, void* const* psi_devs, long nsteps) {
   e->args_ok = true;
   int rc = e->dtype == SGP_C64 ? ens_step_impl<float>(e, nsteps) : ens_step_impl<double>(e, nsteps);
   if (rc == SGP_OK) e->t += nsteps * e->tau;
+  return rc;
+}
+
+int sgp_ensemble_set_plan(sgp_ensemble* e, int n, int axis, int elems) {
+  if (!e) return SGP_ERR_ARG;
+  if (axis < 0 || axis > 1) return efail(e, SGP_ERR_ARG, "axis must be 0 (x) or 1 (y)");
+  bool any = false;
+  for (auto* c : e->ctx) {
+    if (c->g.n[0] != n) continue;
+    const int w = elems == 0 ? default_elems(n) : elems;
+    if (!batched_plan_ok(n, w, (int)c->esize))
+      return efail(e, SGP_ERR_ARG, "plan width " + std::to_string(w) + " not available for batched length " +
+                                       std::to_string(n));
+    int rc = c->dtype == SGP_C64 ? set_plan_impl<float>(c, axis, w) : set_plan_impl<double>(c, axis, w);
+    if (rc != SGP_OK) return efail(e, rc, c->err);
+    any = true;
+  }
+  if (!any) return efail(e, SGP_ERR_ARG, "no instance of length " + std::to_string(n));
+  if (e->ws) {
+    hipError_t r = ens_build_items(e);
+    if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "work list upload");
+  }
+  drop_egraph(e);
+  return SGP_OK;
+}
+
+int sgp_ensemble_get_plan(const sgp_ensemble* e, int n, int axis, int* elems) {
+  if (!e || !elems || axis < 0 || axis > 1) return SGP_ERR_ARG;
+  for (auto* c : e->ctx)
+    if (c->g.n[0] == n) {
+      *elems = c->plan_e[axis];
+      return SGP_OK;
+    }
+  return SGP_ERR_ARG;
+}
+
+int sgp_ensemble_autotune(sgp_ensemble* e, void* const* psi_devs, int steps, double* ms_per_step) {
+  if (!e || !psi_devs) return efail(e, SGP_ERR_ARG, "null argument");
+  if (steps < 1) return efail(e, SGP_ERR_ARG, "steps must be >= 1");
+  if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
+  if (e->scheme == 0) return efail(e, SGP_ERR_STATE, "propagator not built");
+  const double t_save = e->t;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t r = hipEventCreate(&e0);
+  if (r == hipSuccess) r = hipEventCreate(&e1);
+  if (r != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return efail(e, SGP_ERR_HIP, "event create");
+  }
+  auto time_steps = [&](double* ms) -> int {
+    int rc = sgp_ensemble_step(e, psi_devs, steps);  // untimed: graph capture, warm caches
+    if (rc != SGP_OK) return rc;
+    hipError_t q = hipEventRecord(e0, e->st);
+    if (q != hipSuccess) return efail(e, SGP_ERR_HIP, "event record");
+    rc = sgp_ensemble_step(e, psi_devs, steps);
+    if (rc != SGP_OK) return rc;
+    q = hipEventRecord(e1, e->st);
+    if (q == hipSuccess) q = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (q == hipSuccess) q = hipEventElapsedTime(&f, e0, e1);
+    if (q != hipSuccess) return efail(e, SGP_ERR_HIP, "autotune timing");
+    *ms = (double)f / steps;
+    return SGP_OK;
+  };
+  std::vector<int> sizes;
+  for (auto* c : e->ctx)
+    if (std::find(sizes.begin(), sizes.end(), c->g.n[0]) == sizes.end()) sizes.push_back(c->g.n[0]);
+  double best = 0.0;
+  int rc = time_steps(&best);
+  const int esize = e->dtype == SGP_C64 ? 4 : 8;
+  for (size_t k = 0; k < sizes.size() && rc == SGP_OK; ++k)
+    for (int ax = 0; ax < 2 && rc == SGP_OK; ++ax) {
+      const int n = sizes[k];
+      int start = 0;
+      sgp_ensemble_get_plan(e, n, ax, &start);
+      int best_w = start;
+      for (int w : kPlanElems) {
+        if (w == start || !batched_plan_ok(n, w, esize)) continue;
+        double ms = 0.0;
+        rc = sgp_ensemble_set_plan(e, n, ax, w);
+        if (rc == SGP_OK) rc = time_steps(&ms);
+        if (rc != SGP_OK) break;
+        if (ms < best) { best = ms; best_w = w; }
+      }
+      if (rc == SGP_OK) rc = sgp_ensemble_set_plan(e, n, ax, best_w);
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  e->t = t_save;
+  if (rc == SGP_OK && ms_per_step) *ms_per_step = best;
   return rc;
 }
 

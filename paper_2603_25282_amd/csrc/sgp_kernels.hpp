@@ -7,7 +7,11 @@ namespace sgp {
 enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, C_INV = 6,
        // adjoints: of X_FIRST (iFFT, NL adjoint), of X_MID (iFFT, NL adjoint, FFT),
        // of X_LAST (NL adjoint, FFT), of C_PROP (FFT, P^H and parameter partials, iFFT)
-       XA_FIRST = 7, XA_MID = 8, XA_LAST = 9, C_ADJ = 10 };
+       XA_FIRST = 7, XA_MID = 8, XA_LAST = 9, C_ADJ = 10,
+       // rotation mapping (RSDA shears, Sec. 3.1): FFT, phase exp(i nu a w), inverse FFT
+       // along x (w = y of the line) or along y (w = x of the column); and bare
+       // transforms along x (for the lab-frame Algorithm 1 mode)
+       X_SHEAR = 11, C_SHEAR = 12, X_FWD = 13, X_INV = 14 };
 enum { NGRAD = 5 };  // adjoint parameter slots: gamma, Omega, c0, c1, c2
 enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2 };
 enum { CLOCK_ARG = 0, CLOCK_DEVICE = 1 };
@@ -55,6 +59,10 @@ struct PassArgs {
   void* store;           // forward: where to write the pointwise-stage input (or null)
   const void* fwd;       // adjoint: the stored pointwise-stage input of the forward pass
   double* gacc;          // adjoint: per-block parameter slots [block][NGRAD], accumulated
+  // rotation mapping
+  double shear;          // shear coefficient a: f(x, y) <- f(x + a y, y) (x) or f(x, y + a x) (y)
+  double cphase;         // component phase: psi_l *= exp(i l cphase) when cphase_on
+  int cphase_on;
 };
 
 // Register plans of the FFT line kernels: E elements per thread of a line of
@@ -87,10 +95,12 @@ hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e
 template <typename T>
 hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, const int* n, const double* L,
                                int dim, double Omega, double gamma, double d, hipStream_t st);
-// batched passes (default plans): items = int2 (instance, tile), args = PassArgs per instance
+// Plans the batched ensemble kernels run: the 320-thread geometry (n/e <= 64).
+constexpr bool batched_plan_ok(int n, int e, int esize) { return n >= 64 && plan_ok(n, e, esize) && n / e <= 64; }
+// batched passes of one plan width e: items = int2 (instance, tile) of instances
+// using width e along the pass's axis, args = PassArgs per instance
 template <typename T>
-hipError_t launch_pass_batched(int kind, const void* items, const void* args, long nitems, hipStream_t st);
-int batched_lines_per_block(int n);
+hipError_t launch_pass_batched(int kind, int e, const void* items, const void* args, long nitems, hipStream_t st);
 
 // per-plan-width launchers, each (T, E) compiled in its own translation unit
 template <typename T, int E>

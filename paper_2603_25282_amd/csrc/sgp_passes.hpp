@@ -61,15 +61,18 @@ __device__ __forceinline__ void trap_angle(const PassArgs& a, double& c, double&
 // ---------------------------------------------------------------------------
 template <int KIND> struct KindInfo {
   static constexpr bool XL = KIND == X_FIRST || KIND == X_MID || KIND == X_LAST || KIND == X_NLONLY ||
-                             KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
+                             KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST || KIND == X_SHEAR ||
+                             KIND == X_FWD || KIND == X_INV;
+  static constexpr bool SHEAR = KIND == X_SHEAR || KIND == C_SHEAR;
   static constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
   static constexpr bool ADJ = XADJ || KIND == C_ADJ;
-  static constexpr bool PW = XL || KIND == C_PROP || KIND == C_ADJ;  // has a pointwise stage
+  static constexpr bool PW = (XL && !SHEAR && KIND != X_FWD && KIND != X_INV) || KIND == C_PROP ||
+                             KIND == C_ADJ;  // has a pointwise stage (on the LDS tile)
   // which transforms the pass runs (forward: exp(-i..), inverse: exp(+i..))
   static constexpr bool HF = KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST ||
-                             KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ;
+                             KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || SHEAR || KIND == X_FWD;
   static constexpr bool HI = KIND == X_MID || KIND == X_LAST || KIND == XA_FIRST || KIND == XA_MID ||
-                             KIND == C_PROP || KIND == C_INV || KIND == C_ADJ;
+                             KIND == C_PROP || KIND == C_INV || KIND == C_ADJ || SHEAR || KIND == X_INV;
 };
 
 // LDS cx<T> values of the staged twiddle tables of a pass (forward table first).
@@ -144,9 +147,38 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
   if constexpr (TWF > 0) stage_tw<T, NT, TWF>(ltw, a.tw_fwd, tid);
   if constexpr (TWI > 0) stage_tw<T, NT, TWI>(ltw + TWF, a.tw_inv, tid);
 
-  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID)
+  if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID ||
+                KIND == X_INV)
     fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
-  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ) fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || KIND == X_FWD || KindInfo<KIND>::SHEAR)
+    fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+
+  if constexpr (KindInfo<KIND>::SHEAR) {
+    // f(.. + a w ..) along the line: coefficient k times exp(i nu_k a w) / N, w the
+    // line's coordinate on the other in-plane axis; FP64 phase
+    double w;
+    if constexpr (XL) {
+      const int line = (int)line0 + col;
+      const int iy = a.dim == 3 ? line - (line / a.ny) * a.ny : line;
+      w = -a.L[1] + iy * a.h[1];
+    } else {
+      w = -a.L[0] + (kx0 + col) * a.h[0];
+    }
+    const double nus = XL ? a.nu_scale_a : a.nu_scale_l;
+    double cr = 1.0, ci = 0.0;
+    if (a.cphase_on) sincos((2 - c) * a.cphase, &ci, &cr);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = t + TL * m;
+      const int p = k < N / 2 ? k : k - N;
+      double sn, cs;
+      sincos(p * nus * a.shear * w, &sn, &cs);
+      const double zr = (cs * cr - sn * ci) / N, zi = (cs * ci + sn * cr) / N;
+      const T vr = v[0][m].re, vi = v[0][m].im;
+      v[0][m] = mk<T>(T(zr) * vr - T(zi) * vi, T(zr) * vi + T(zi) * vr);
+    }
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+  }
 
   // forward store mode: keep the pointwise-stage input for the adjoint
   if constexpr (PW && !ADJ) {
@@ -332,7 +364,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
 #pragma unroll
     for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
   }
-  if constexpr (XL && !ADJ) {
+  if constexpr (XL && !ADJ && PW) {
     if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) {
       a.clock[0] = a.s_arg;
       double sn, cn;
@@ -368,31 +400,51 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
 
 // ---------------------------------------------------------------------------
 // Batched pass over many grids (an ensemble): block b processes work item
-// items[b] = (instance, tile) with that instance's arguments; every line length
-// used runs with 320 threads per block (W = 64 E / N lines per block).
+// items[b] = (instance, tile) with that instance's arguments.  One kernel per plan
+// width E; every line length it serves runs with 320 threads per block (W = 64 E / N
+// lines), the geometry of the single-grid kernel of the same plan, so an instance
+// gives bitwise the same result alone or inside an ensemble.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND>
+template <int N, int E, int KIND, int ES>
+constexpr int batched_lds() {
+  if constexpr (batched_plan_ok(N, E, ES)) return pass_lds<N, lines_per_block(N, E), KIND>();
+  else return 0;
+}
+template <int N, int E, int KIND, int ES>
+constexpr int batched_tw() {
+  if constexpr (batched_plan_ok(N, E, ES)) return pass_tw<N, E, KIND>();
+  else return 0;
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <typename T, int KIND, int E>
 __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
-  constexpr int BUF = pass_lds<384, 2, KIND>() > pass_lds<512, 1, KIND>() ? pass_lds<384, 2, KIND>()
-                                                                           : pass_lds<512, 1, KIND>();
-  constexpr int TW1 = pass_tw<512, 8, KIND>(), TW2 = pass_tw<384, 12, KIND>();
-  constexpr int TWB = ((TW1 > TW2 ? TW1 : TW2) * (int)sizeof(cx<T>) + 15) / 16;
-  __shared__ T lre[BUF];
-  __shared__ T lim[BUF];
+  constexpr int ES = (int)sizeof(T);
+  constexpr int BUF = cmax(cmax(cmax(batched_lds<64, E, KIND, ES>(), batched_lds<128, E, KIND, ES>()),
+                                cmax(batched_lds<256, E, KIND, ES>(), batched_lds<384, E, KIND, ES>())),
+                           batched_lds<512, E, KIND, ES>());
+  constexpr int TWM = cmax(cmax(cmax(batched_tw<64, E, KIND, ES>(), batched_tw<128, E, KIND, ES>()),
+                                cmax(batched_tw<256, E, KIND, ES>(), batched_tw<384, E, KIND, ES>())),
+                           batched_tw<512, E, KIND, ES>());
+  constexpr int TWB = (TWM * (int)sizeof(cx<T>) + 15) / 16;
+  __shared__ T lre[BUF > 0 ? BUF : 1];
+  __shared__ T lim[BUF > 0 ? BUF : 1];
   __shared__ uint4 ltwr[TWB > 0 ? TWB : 1];
   cx<T>* ltw = reinterpret_cast<cx<T>*>(ltwr);
   __shared__ double gred[KindInfo<KIND>::ADJ ? 6 : 1][NGRAD];
   const int2 it = items[blockIdx.x];
   const PassArgs& a = args[it.x];
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.state);
+#define SGP_BCASE(NN)                                                                                  \
+  case NN:                                                                                             \
+    if constexpr (batched_plan_ok(NN, E, ES))                                                          \
+      pass_body<T, NN, E, lines_per_block(NN, E), KIND>(psi, a, it.y, lre, lim, ltw, gred);             \
+    break;
   switch (a.n_line) {
-    case 64: pass_body<T, 64, 8, 8, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
-    case 128: pass_body<T, 128, 8, 4, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
-    case 256: pass_body<T, 256, 8, 2, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
-    case 384: pass_body<T, 384, 12, 2, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
-    case 512: pass_body<T, 512, 8, 1, KIND>(psi, a, it.y, lre, lim, ltw, gred); break;
+    SGP_BCASE(64) SGP_BCASE(128) SGP_BCASE(256) SGP_BCASE(384) SGP_BCASE(512)
     default: break;
   }
+#undef SGP_BCASE
 }
 
 // ---------------------------------------------------------------------------
@@ -652,6 +704,10 @@ static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t
     case XA_MID: return pass_n<T, N, E, XA_MID>(psi, a, st);
     case XA_LAST: return pass_n<T, N, E, XA_LAST>(psi, a, st);
     case C_ADJ: return pass_n<T, N, E, C_ADJ>(psi, a, st);
+    case X_SHEAR: return pass_n<T, N, E, X_SHEAR>(psi, a, st);
+    case C_SHEAR: return pass_n<T, N, E, C_SHEAR>(psi, a, st);
+    case X_FWD: return pass_n<T, N, E, X_FWD>(psi, a, st);
+    case X_INV: return pass_n<T, N, E, X_INV>(psi, a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -703,6 +759,20 @@ hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, dou
   switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
 #undef SGP_CASE
   return hipErrorInvalidValue;
+}
+
+// Batched passes of one plan width (compiled with that width's unit).
+template <typename T, int E>
+hipError_t launch_batched_e(int kind, const int2* it, const PassArgs* ar, long nitems, hipStream_t st) {
+  dim3 g((unsigned)nitems), b(320);
+  switch (kind) {
+    case X_FIRST: hipLaunchKernelGGL((k_pass_batched<T, X_FIRST, E>), g, b, 0, st, it, ar); break;
+    case X_MID: hipLaunchKernelGGL((k_pass_batched<T, X_MID, E>), g, b, 0, st, it, ar); break;
+    case X_LAST: hipLaunchKernelGGL((k_pass_batched<T, X_LAST, E>), g, b, 0, st, it, ar); break;
+    case C_PROP: hipLaunchKernelGGL((k_pass_batched<T, C_PROP, E>), g, b, 0, st, it, ar); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace sgp

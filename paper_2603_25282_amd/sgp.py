@@ -22,6 +22,8 @@ SGP_TS2, SGP_TS4 = 2, 4
 SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
 SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
 SGP_TIME_IN_STEP = 256
+SGP_OPT_FRAME = 3
+SGP_FRAME_ROTATING, SGP_FRAME_LAB = 0, 1
 
 
 class SgpError(RuntimeError):
@@ -65,6 +67,7 @@ def lib():
     L.sgp_adjoint_gradients.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     ip = ctypes.POINTER(ctypes.c_int)
     L.sgp_plan_widths.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int]
+    L.sgp_rotation_map.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int]
     L.sgp_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sgp_get_plan.argtypes = [vp, ctypes.c_int, ip]
     L.sgp_autotune.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
@@ -81,9 +84,10 @@ def exported_symbols():
     return ["sgp_create", "sgp_workspace_size", "sgp_set_workspace", "sgp_build_propagator", "sgp_step",
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
             "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
-            "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune",
+            "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune", "sgp_rotation_map",
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
+            "sgp_ensemble_set_plan", "sgp_ensemble_get_plan", "sgp_ensemble_autotune",
             "sgp_ensemble_last_error"]
 
 
@@ -270,6 +274,15 @@ class Solver:
                 pass
         return widths, ms.value
 
+    def rotation_map(self, psi, t, direction):
+        """In place: direction +1 lab -> rotating frame (Phi = M_t Psi), -1 back."""
+        _check(lib().sgp_rotation_map(self._ctx, self._psi_ptr(psi), float(t), int(direction)), self._ctx)
+
+    def set_frame(self, frame):
+        """'rotating' (default) or 'lab' (Algorithm 1 literally on the lab-frame state)."""
+        v = {"rotating": SGP_FRAME_ROTATING, "lab": SGP_FRAME_LAB}[frame]
+        _check(lib().sgp_set_option(self._ctx, SGP_OPT_FRAME, v), self._ctx)
+
     def set_graph(self, on):
         _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)
 
@@ -313,6 +326,9 @@ class Ensemble:
         L.sgp_ensemble_build_propagator.argtypes = [vp, ctypes.c_double, ctypes.c_int]
         L.sgp_ensemble_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_long]
         L.sgp_ensemble_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_long]
+        L.sgp_ensemble_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.sgp_ensemble_get_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.sgp_ensemble_autotune.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.sgp_ensemble_destroy.argtypes = [vp]
         L.sgp_ensemble_destroy.restype = None
         L.sgp_ensemble_last_error.argtypes = [vp]
@@ -357,6 +373,28 @@ class Ensemble:
 
     def set_option(self, option, value):
         self._chk(lib().sgp_ensemble_set_option(self._h, int(option), int(value)))
+
+    def set_plan(self, n, axis, elems):
+        """Plan width along axis (0 x, 1 y) of every instance of size n x n (0 = default)."""
+        self._chk(lib().sgp_ensemble_set_plan(self._h, int(n), int(axis), int(elems)))
+
+    def get_plan(self, n, axis):
+        e = ctypes.c_int()
+        self._chk(lib().sgp_ensemble_get_plan(self._h, int(n), int(axis), ctypes.byref(e)))
+        return e.value
+
+    def plans(self):
+        """{n: (x width, y width)} over the instance sizes."""
+        return {n: (self.get_plan(n, 0), self.get_plan(n, 1)) for n in sorted({sh[0] for sh in self.shapes})}
+
+    def autotune(self, psis, steps=10):
+        """sgp_ensemble_autotune on scratch copies of psis; returns (plans(), ms per step)."""
+        scratch = [p.clone() for p in psis]
+        arr = (ctypes.c_void_p * len(scratch))(*[p.data_ptr() for p in scratch])
+        ms = ctypes.c_double()
+        self._chk(lib().sgp_ensemble_autotune(self._h, arr, int(steps), ctypes.byref(ms)))
+        del scratch
+        return self.plans(), ms.value
 
     def close(self):
         if getattr(self, "_h", None):

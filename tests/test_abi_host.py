@@ -102,3 +102,35 @@ def test_plan_widths_and_plan_setters_without_device():
     assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 5, outw, None) == -2  # no workspace yet
     assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 0, outw, None) == -1
     L.sgp_destroy(ctx)
+
+
+def test_ensemble_plan_setters_without_device():
+    L = sgp.lib()
+    grids = (sgp._Grid * 3)()
+    pars = (sgp._Params * 3)()
+    for i, n in enumerate((128, 512, 128)):
+        grids[i].dim = 2
+        grids[i].n[0] = grids[i].n[1] = n
+        grids[i].n[2] = 1
+        grids[i].L[0] = grids[i].L[1] = 8.0
+        pars[i] = sgp._Params(1, 1, 1, 0.5, 0.5, 1, 1, 1)
+    L.sgp_ensemble_create.argtypes = [ctypes.c_int, ctypes.POINTER(sgp._Grid), ctypes.POINTER(sgp._Params),
+                                      ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.sgp_ensemble_set_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.sgp_ensemble_get_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.sgp_ensemble_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double)]
+    L.sgp_ensemble_destroy.argtypes = [ctypes.c_void_p]
+    L.sgp_ensemble_destroy.restype = None
+    h = ctypes.c_void_p()
+    assert L.sgp_ensemble_create(3, grids, pars, 0, None, ctypes.byref(h)) == 0
+    e = ctypes.c_int()
+    assert L.sgp_ensemble_get_plan(h, 128, 0, ctypes.byref(e)) == 0 and e.value == 8
+    assert L.sgp_ensemble_set_plan(h, 128, 1, 16) == 0
+    assert L.sgp_ensemble_get_plan(h, 128, 1, ctypes.byref(e)) == 0 and e.value == 16
+    assert L.sgp_ensemble_set_plan(h, 512, 0, 4) == -1  # 640-thread geometry: not batched
+    assert L.sgp_ensemble_set_plan(h, 256, 0, 8) == -1  # no instance of that size
+    assert L.sgp_ensemble_set_plan(h, 128, 2, 8) == -1
+    ptrs = (ctypes.c_void_p * 3)(1, 2, 3)
+    assert L.sgp_ensemble_autotune(h, ptrs, 4, None) == -2  # no workspace
+    L.sgp_ensemble_destroy(h)

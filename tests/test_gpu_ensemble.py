@@ -86,3 +86,58 @@ def test_full_ensemble_workload_consistency():
         err = rel_l2(got, ref)
         print(f"instance {k} {c.shape} rel l2 {err:.3e}")
         assert err <= 5e-5
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_ensemble_with_plans_batched_equals_unbatched(dtype):
+    # non-default plans per size and axis: two batched launches per pass type (two
+    # widths in use); still bitwise equal to the per-instance runs, and the oracle
+    import torch
+    from paper_2603_25282_amd.sgp import SGP_OPT_BATCHED, Solver
+    insts = I.ensemble_instances(seed=4, n128=2, n256=1, n384=1, L=12.0, order=4, tau=1e-3, steps=0)
+    insts = [I.with_(insts[0], shape=(64, 64), L=8.0, name="e64")] + insts
+    plans = {64: (16, 4), 128: (4, 16), 256: (16, 8), 384: (12, 24 if dtype == "complex64" else 12)}
+    nsteps = 18
+    out = []
+    for batched in (1, 0):
+        ens, psis = make(insts, dtype)
+        for n, (ex, ey) in plans.items():
+            ens.set_plan(n, 0, ex)
+            ens.set_plan(n, 1, ey)
+        assert ens.plans() == plans
+        ens.build_propagator(1e-3, 4)
+        ens.set_option(SGP_OPT_BATCHED, batched)
+        print(f"case ensemble plans {plans} {dtype} batched={batched}", flush=True)
+        ens.step(psis, nsteps)
+        torch.cuda.synchronize()
+        out.append([p.cpu().numpy() for p in psis])
+    for k, c in enumerate(insts):
+        assert np.array_equal(out[0][k], out[1][k]), f"instance {k} ({c.shape}) batched != unbatched"
+    tol = 1e-11 if dtype == "complex128" else 5e-5
+    for k in (0, 1, 3, 4):
+        c = insts[k]
+        ref = oracle.evolve(I.initial_state(c), c.L, c.params, 4, 1e-3, nsteps)
+        err = rel_l2(Solver.from_device_layout(out[0][k].astype(np.complex128)), ref)
+        print(f"instance {k} {c.shape} rel l2 {err:.3e}")
+        assert err <= tol
+
+
+def test_ensemble_autotune():
+    import torch
+    from paper_2603_25282_amd.sgp import Solver
+    insts = I.ensemble_instances(seed=4, n128=4, n256=2, n384=1, L=12.0, order=2, tau=1e-3, steps=0)
+    ens, psis = make(insts, "complex64")
+    ens.build_propagator(1e-3, 2)
+    before = [p.clone() for p in psis]
+    plans, ms = ens.autotune(psis, steps=4)
+    print("ensemble plans", plans, "ms/step", ms, flush=True)
+    assert ms > 0 and set(plans) == {128, 256, 384}
+    for k in range(len(psis)):
+        assert torch.equal(psis[k], before[k])  # tuned on scratch copies
+    ens.step(psis, 6)
+    torch.cuda.synchronize()
+    c = insts[-1]
+    ref = oracle.evolve(I.initial_state(c), c.L, c.params, 2, 1e-3, 6)
+    err = rel_l2(Solver.from_device_layout(psis[-1].cpu().numpy().astype(np.complex128)), ref)
+    print("384 instance after autotune rel l2", err)
+    assert err <= 5e-5
