@@ -111,6 +111,16 @@ int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
  * FP64 accumulation.  Synchronous. */
 int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
 
+/* The observables plus the quantities of the dynamical laws of Sec. 2, all FP64:
+ * out[0..3] as sgp_observables; out[4], out[5], out[6] = the widths delta_x,
+ * delta_y, delta_z (eq. ConWid: h^d sum alpha^2 rho, alpha the lab-frame coordinate
+ * of the point, i.e. (x, y) rotated by Omega t in the rotating frame; delta_z = 0
+ * in 2D); out[7] = h^d sum x y rho (lab frame; Lemma 1: d<Lz>/dt =
+ * (gx^2 - gy^2) out[7] when gamma = 0); out[8] = W = 2 h^d Im sum conj(psi)
+ * (x d_x + y d_y) psi with spectral derivatives, which equals d(delta_x +
+ * delta_y)/dt when gamma = 0 (Lemma 2).  Synchronous. */
+int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[9]);
+
 /* ---- Differentiation (discrete adjoint of sgp_step) -------------------------
  * Convention: for a real loss J of the state, a gradient is g = 2 dJ/d conj(psi),
  * i.e. dJ = Re sum conj(g) dpsi over all stored values (the convention of

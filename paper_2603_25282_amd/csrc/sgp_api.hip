@@ -547,7 +547,7 @@ long pass_nblocks(const sgp_ctx* c, int axis, int e) {
 }
 
 template <typename T>
-int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
+int observables_impl(sgp_ctx* c, const void* psi, double out[9]) {
   double* part = (double*)c->at(c->off_part);
   double tot[3][NOBS];
   for (int axis = 0; axis < c->g.dim; ++axis) {
@@ -584,6 +584,12 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[4]) {
   out[2] = hd * tot[0][1];
   out[3] = hd * lz;
   out[1] = hd * (ekin + tot[0][2] + tot[0][3] - c->p.gamma * soc) - c->p.Omega * out[3];
+  // widths and moments (lab-frame coordinates) and W = 2 Im sum conj(psi)(x d_x + y d_y) psi
+  out[4] = hd * tot[0][7];
+  out[5] = hd * tot[0][8];
+  out[6] = hd * tot[0][9];
+  out[7] = hd * tot[0][10];
+  out[8] = hd * (tot[0][11] + tot[1][11]);
   return SGP_OK;
 }
 
@@ -871,6 +877,15 @@ int sgp_rotation_map(sgp_ctx* c, void* psi, double t, int direction) {
 }
 
 int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
+  if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  double all[9];
+  int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
+  if (rc == SGP_OK) std::memcpy(out, all, 4 * sizeof(double));
+  return rc;
+}
+
+int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[9]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   return c->dtype == SGP_C64 ? observables_impl<float>(c, psi, out) : observables_impl<double>(c, psi, out);

@@ -452,9 +452,12 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
 // OBS_X (lines along x): d_x psi spectrally; per point the mass, the
 //   magnetization, V|psi|^2, the interaction energy, |d_x psi|^2/2,
 //   Re(conj(psi) i y d_x psi) (the y d_x part of -i(x d_y - y d_x)) and
-//   Re(psi^H K d_x psi);
+//   Re(psi^H K d_x psi); the moments X^2 rho, Y^2 rho, z^2 rho, X Y rho at the
+//   rotated point (X, Y) = R(Omega s) (x, y) (the lab-frame coordinates of the
+//   point, Sec. 2, eq. ConWid) and 2 x Im(conj(psi) d_x psi);
 // OBS_Y / OBS_Z (columns): d_y psi (or d_z psi); |d psi|^2/2,
-//   Re(conj(psi) (-i x) d_y psi) and Re(i psi^H M d_y psi) (y only).
+//   Re(conj(psi) (-i x) d_y psi), Re(i psi^H M d_y psi) and 2 y Im(conj(psi) d_y psi)
+//   (y only).
 // With L+- = i d_y +- d_x the SOC matrix is S = i d_y M + d_x K, M symmetric with
 // the weights (1, sqrt6/2, sqrt6/2, 1) on both off-diagonals, K = -M above and +M
 // below the diagonal.
@@ -545,7 +548,8 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
     } else {
       on = kx0 + pc < a.ncols;
       x = -a.L[0] + (kx0 + pc) * a.h[0];
-      y = z = 0.0;
+      y = KIND == OBS_Y ? -a.L[1] + j * a.h[1] : 0.0;
+      z = 0.0;
     }
     if (!on) continue;
     double pr[5], pi[5], dr[5], di[5];
@@ -595,6 +599,11 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
       acc[4] += 0.5 * grad2;
       acc[5] += -y * rot;  // Re(conj(psi) (i y) d_x psi)
       acc[6] += soc;
+      acc[7] += X * X * rho;
+      acc[8] += Y * Y * rho;
+      acc[9] += z * z * rho;
+      acc[10] += X * Y * rho;
+      acc[11] += 2.0 * x * rot;
     } else {
       acc[4] += 0.5 * grad2;
       if constexpr (KIND == OBS_Y) {
@@ -605,6 +614,7 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
         for (int l = 0; l < 4; ++l)
           s += w[l] * ((pr[l] * di[l + 1] - pi[l] * dr[l + 1]) + (pr[l + 1] * di[l] - pi[l + 1] * dr[l]));
         acc[6] += -s;
+        acc[11] += 2.0 * y * rot;
       }
     }
   }

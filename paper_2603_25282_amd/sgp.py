@@ -68,6 +68,7 @@ def lib():
     ip = ctypes.POINTER(ctypes.c_int)
     L.sgp_plan_widths.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int]
     L.sgp_rotation_map.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int]
+    L.sgp_diagnostics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     L.sgp_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sgp_get_plan.argtypes = [vp, ctypes.c_int, ip]
     L.sgp_autotune.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
@@ -85,6 +86,7 @@ def exported_symbols():
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
             "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
             "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune", "sgp_rotation_map",
+            "sgp_diagnostics",
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
             "sgp_ensemble_set_plan", "sgp_ensemble_get_plan", "sgp_ensemble_autotune",
@@ -183,6 +185,14 @@ class Solver:
         out = (ctypes.c_double * 4)()
         _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
         return np.array(out[:])
+
+    def diagnostics(self, psi):
+        """sgp_diagnostics as a dict: mass, energy, magnetization, lz, delta_x,
+        delta_y, delta_z, xy_rho, width_rate (= d delta_r/dt when gamma = 0)."""
+        out = (ctypes.c_double * 9)()
+        _check(lib().sgp_diagnostics(self._ctx, self._psi_ptr(psi), out), self._ctx)
+        keys = ("mass", "energy", "magnetization", "lz", "delta_x", "delta_y", "delta_z", "xy_rho", "width_rate")
+        return dict(zip(keys, out[:]))
 
     def time_pass(self, psi, pass_kind, reps, in_step=False):
         """Average milliseconds of one pass (0 X, 1 Y, 2 Z, 3 inverse Y) over reps
