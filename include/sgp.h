@@ -57,7 +57,10 @@ enum {
 };
 
 enum { SGP_C64 = 0, SGP_C128 = 1 };  /* element type of the state */
-enum { SGP_TS2 = 2, SGP_TS4 = 4 };   /* time composition (Sec. 3.3) */
+/* Time composition (Sec. 3.3): TS2 Strang, TS4 the 4th-order symplectic scheme,
+ * TS6 the 6th-order triple jump S4(z1 tau) S4(z0 tau) S4(z1 tau) of TS4 (Yoshida's
+ * composition, which the section cites), z1 = 1/(2 - 2^(1/5)), z0 = -2^(1/5) z1. */
+enum { SGP_TS2 = 2, SGP_TS4 = 4, SGP_TS6 = 6 };
 
 typedef struct sgp_ctx sgp_ctx;
 
@@ -90,7 +93,8 @@ int sgp_set_workspace(sgp_ctx* ctx, void* dev_ptr, size_t bytes);
 /* Build, in FP64 on the device, the exact linear propagator
  * exp(-i d |nu|^2 / 2) exp(i d Q) (Sec. 3.1, eq. sl1 and the closed form of
  * exp(i tau Q), precomputed once as in Remark comput-cost) for every distinct linear
- * substep d of the scheme: TS2 {tau}, TS4 {b1 tau, b2 tau}.  The tables are stored
+ * substep d of the scheme: TS2 {tau}, TS4 {b1 tau, b2 tau}, TS6 {z1 b1, z1 b2, z0 b1,
+ * z0 b2} tau.  The tables are stored
  * rounded to the state's precision.  tau may be negative (backward evolution).
  * Synchronous. */
 int sgp_build_propagator(sgp_ctx* ctx, double tau, int scheme);

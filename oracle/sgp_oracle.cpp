@@ -468,22 +468,41 @@ static void rotation_map(const OGrid& g, const OParams& P, double t, bool forwar
 // Lab frame (mode 1): Algorithm 1 literally, the mapping M_s before and M_{s+d}^{-1}
 // after every linear substep, the nonlinear substep with the lab trap.
 // ---------------------------------------------------------------------------
-struct Scheme { int m; double a[4]; double b[4]; };
+// Order 6: Yoshida's triple jump of the 4th-order scheme, S6(tau) = S4(z1 tau)
+// S4(z0 tau) S4(z1 tau), z1 = 1/(2 - 2^(1/5)), z0 = -2^(1/5)/(2 - 2^(1/5)); the
+// nonlinear flows that meet where two S4 factors join (same clock) are one flow of
+// the summed length.
+struct Scheme { int m; double a[10]; double b[10]; };
 
 static Scheme make_scheme(int order) {
   Scheme sc;
   if (order == 2) {
     sc.m = 2; sc.a[0] = 0.5; sc.a[1] = 0.5; sc.b[0] = 1.0; sc.b[1] = 0.0;
-  } else {
-    double c = std::cbrt(2.0);
-    double den = 2.0 - c;
-    sc.m = 4;
-    sc.a[0] = sc.a[3] = 1.0 / (2.0 * den);
-    sc.a[1] = sc.a[2] = (1.0 - c) / (2.0 * den);
-    sc.b[0] = sc.b[2] = 1.0 / den;
-    sc.b[1] = -c / den;
-    sc.b[3] = 0.0;
+    return sc;
   }
+  double c = std::cbrt(2.0);
+  double den = 2.0 - c;
+  const double a4[4] = {1.0 / (2.0 * den), (1.0 - c) / (2.0 * den), (1.0 - c) / (2.0 * den), 1.0 / (2.0 * den)};
+  const double b4[4] = {1.0 / den, -c / den, 1.0 / den, 0.0};
+  if (order == 4) {
+    sc.m = 4;
+    for (int j = 0; j < 4; ++j) { sc.a[j] = a4[j]; sc.b[j] = b4[j]; }
+    return sc;
+  }
+  const double q = std::pow(2.0, 0.2);
+  const double z[3] = {1.0 / (2.0 - q), -q / (2.0 - q), 1.0 / (2.0 - q)};
+  sc.m = 0;
+  for (int f = 0; f < 3; ++f)
+    for (int j = 0; j < 4; ++j) {
+      if (j == 0 && f > 0) {
+        sc.a[sc.m - 1] += z[f] * a4[0];  // joins the previous factor's last flow
+        sc.b[sc.m - 1] = z[f] * b4[0];
+        continue;
+      }
+      sc.a[sc.m] = z[f] * a4[j];
+      sc.b[sc.m] = z[f] * b4[j];
+      ++sc.m;
+    }
   return sc;
 }
 

@@ -81,8 +81,8 @@ struct sgp_ctx {
   size_t ws_bytes = 0;
   size_t total = 0;
   size_t off_tw[3][2];
-  size_t off_cs[2];
-  size_t off_kin[2][3];
+  size_t off_cs[4];      // (C - 1, S) table per distinct linear substep length
+  size_t off_kin[4][3];
   size_t off_clock;
   size_t off_part;
   size_t off_gacc;
@@ -96,7 +96,7 @@ struct sgp_ctx {
   int scheme = 0;
   double tau = 0.0;
   int nprop = 0;
-  double dprop[2] = {0, 0};
+  double dprop[4] = {0, 0, 0, 0};
   bool have_prop = false;
   double t = 0.0;
   std::string err;
@@ -282,30 +282,69 @@ hipError_t run_linear(sgp_ctx* c, hipStream_t st, void* psi, int table, double d
   return run_colpass<T>(c, st, C_INV, 1, psi, table, d);
 }
 
-// Substep schedule of nsteps steps with merged adjacent nonlinear substeps:
-// nl has one more entry than lin; lin_tab selects the propagator table.
+// One step of a composition (Sec. 3.3): nonlinear flows A[j] tau and linear flows
+// B[j] tau alternate, N(A[0]) L(B[0]) N(A[1]) ... L(B[m-2]) N(A[m-1]) (B[m-1] = 0);
+// tab[j] is the propagator table of L(B[j]) and props the distinct B values (one
+// table each).  TS6 is the triple jump S4(z1) S4(z0) S4(z1), z1 = 1/(2 - 2^(1/5)),
+// z0 = -2^(1/5) z1, the nonlinear flows that meet at a join being one flow.
+struct Composition {
+  std::vector<double> A, B, props;
+  std::vector<int> tab;
+};
+
+Composition composition(int scheme) {
+  Composition k;
+  if (scheme == SGP_TS2) {
+    k.A = {0.5, 0.5};
+    k.B = {1.0, 0.0};
+  } else {
+    TS4 f;
+    const std::vector<double> a4 = {f.a1, f.a2, f.a2, f.a1}, b4 = {f.b1, f.b2, f.b1, 0.0};
+    if (scheme == SGP_TS4) {
+      k.A = a4;
+      k.B = b4;
+    } else {
+      const double q = std::pow(2.0, 0.2);
+      const double z[3] = {1.0 / (2.0 - q), -q / (2.0 - q), 1.0 / (2.0 - q)};
+      for (int fi = 0; fi < 3; ++fi)
+        for (int j = 0; j < 4; ++j) {
+          if (j == 0 && fi > 0) {
+            k.A.back() += z[fi] * a4[0];
+            k.B.back() = z[fi] * b4[0];
+            continue;
+          }
+          k.A.push_back(z[fi] * a4[j]);
+          k.B.push_back(z[fi] * b4[j]);
+        }
+    }
+  }
+  for (double b : k.B) {
+    if (b == 0.0) { k.tab.push_back(-1); continue; }
+    size_t i = 0;
+    while (i < k.props.size() && k.props[i] != b) ++i;
+    if (i == k.props.size()) k.props.push_back(b);
+    k.tab.push_back((int)i);
+  }
+  return k;
+}
+
+// Substep schedule of nsteps steps with merged adjacent nonlinear substeps (the last
+// flow of a step and the first of the next share the clock): nl has one more entry
+// than lin; lin_tab selects the propagator table.
 void schedule(const sgp_ctx* c, long nsteps, std::vector<double>& nl, std::vector<double>& lin,
               std::vector<int>& lin_tab) {
   const double tau = c->tau;
   nl.clear(); lin.clear(); lin_tab.clear();
-  if (c->scheme == SGP_TS2) {
-    nl.push_back(0.5 * tau);
-    for (long n = 0; n < nsteps; ++n) {
-      lin.push_back(tau); lin_tab.push_back(0);
-      nl.push_back(n + 1 < nsteps ? tau : 0.5 * tau);
+  const Composition k = composition(c->scheme);
+  const size_t m = k.A.size();
+  nl.push_back(k.A[0] * tau);
+  for (long n = 0; n < nsteps; ++n)
+    for (size_t j = 0; j + 1 < m; ++j) {
+      lin.push_back(k.B[j] * tau);
+      lin_tab.push_back(k.tab[j]);
+      if (j + 2 < m) nl.push_back(k.A[j + 1] * tau);
+      else nl.push_back(n + 1 < nsteps ? (k.A[m - 1] + k.A[0]) * tau : k.A[m - 1] * tau);
     }
-  } else {
-    TS4 k;
-    nl.push_back(k.a1 * tau);
-    for (long n = 0; n < nsteps; ++n) {
-      lin.push_back(k.b1 * tau); lin_tab.push_back(0);
-      nl.push_back(k.a2 * tau);
-      lin.push_back(k.b2 * tau); lin_tab.push_back(1);
-      nl.push_back(k.a2 * tau);
-      lin.push_back(k.b1 * tau); lin_tab.push_back(0);
-      nl.push_back(n + 1 < nsteps ? 2.0 * k.a1 * tau : k.a1 * tau);
-    }
-  }
 }
 
 // The periodic middle of a call: one whole step that starts after a merged
@@ -633,18 +672,10 @@ int rotation_map_impl(sgp_ctx* c, void* psi, double t, int dir) {
 // same propagator pass, between bare transforms along x.
 template <typename T>
 int lab_step_impl(sgp_ctx* c, void* psi, long nsteps) {
-  std::vector<double> A, B;
-  std::vector<int> tab;
-  if (c->scheme == SGP_TS2) {
-    A = {0.5, 0.5};
-    B = {1.0, 0.0};
-    tab = {0, 0};
-  } else {
-    TS4 k;
-    A = {k.a1, k.a2, k.a2, k.a1};
-    B = {k.b1, k.b2, k.b1, 0.0};
-    tab = {0, 1, 0, 0};
-  }
+  const Composition comp = composition(c->scheme);
+  const std::vector<double>& A = comp.A;
+  const std::vector<double>& B = comp.B;
+  const std::vector<int>& tab = comp.tab;
   const double t0 = c->t, tau = c->tau;
   for (long n = 0; n < nsteps; ++n) {
     double s = t0 + (double)n * tau;
@@ -773,7 +804,7 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
       if (ax < c->g.dim) off += align256(4 * c->esize * (most + 1));
     }
   const size_t nxy = (size_t)c->g.n[0] * c->g.n[1];
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     c->off_cs[k] = off;
     off += align256(2 * c->esize * nxy);
     for (int ax = 0; ax < 3; ++ax) {
@@ -825,18 +856,15 @@ int sgp_build_propagator(sgp_ctx* c, double tau, int scheme) {
   if (!c) return SGP_ERR_ARG;
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!std::isfinite(tau) || tau == 0.0) return fail(c, SGP_ERR_ARG, "tau must be finite and nonzero");
-  if (scheme != SGP_TS2 && scheme != SGP_TS4) return fail(c, SGP_ERR_ARG, "scheme must be SGP_TS2 or SGP_TS4");
+  if (scheme != SGP_TS2 && scheme != SGP_TS4 && scheme != SGP_TS6)
+    return fail(c, SGP_ERR_ARG, "scheme must be SGP_TS2, SGP_TS4 or SGP_TS6");
   drop_graph(c);
   c->scheme = scheme;
   c->tau = tau;
-  if (scheme == SGP_TS2) {
-    c->nprop = 1;
-    c->dprop[0] = tau;
-  } else {
-    TS4 k;
-    c->nprop = 2;
-    c->dprop[0] = k.b1 * tau;
-    c->dprop[1] = k.b2 * tau;
+  {
+    const Composition comp = composition(scheme);
+    c->nprop = (int)comp.props.size();
+    for (int i = 0; i < c->nprop; ++i) c->dprop[i] = comp.props[i] * tau;
   }
   for (int i = 0; i < c->nprop; ++i) {
     hipError_t e;
@@ -917,7 +945,7 @@ int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
 int sgp_store_size(const sgp_ctx* c, long nsteps, size_t* bytes) {
   if (!c || !bytes || nsteps < 1) return SGP_ERR_ARG;
   if (c->scheme == 0) return SGP_ERR_STATE;
-  const long M = (c->scheme == SGP_TS2 ? 1 : 3) * nsteps;
+  const long M = (long)(composition(c->scheme).A.size() - 1) * nsteps;
   *bytes = (size_t)(2 * M + 1) * (size_t)c->npts() * 5 * 2 * c->esize;
   return SGP_OK;
 }
@@ -1297,6 +1325,7 @@ int sgp_ensemble_set_workspace(sgp_ensemble* e, void* dev_ptr, size_t bytes) {
 int sgp_ensemble_build_propagator(sgp_ensemble* e, double tau, int scheme) {
   if (!e) return SGP_ERR_ARG;
   if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
+  if (scheme != SGP_TS2 && scheme != SGP_TS4) return efail(e, SGP_ERR_ARG, "ensembles run SGP_TS2 or SGP_TS4");
   for (int i = 0; i < e->n; ++i) {
     int rc = sgp_build_propagator(e->ctx[i], tau, scheme);
     if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);

@@ -109,33 +109,33 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
   const int col = XL ? rest / TL : rest % W;
   const int t = XL ? rest % TL : rest / W;
 
-  // line geometry
-  long base;        // element offset of the line's first point (component 0)
-  long estride;     // element stride between consecutive points of the line
-  long line0 = 0;   // x-lines: first line of the block (line = z * ny + y)
-  long o = 0, kx0 = 0;
+  // line geometry, in 32-bit element offsets (every supported state, up to
+  // 512^3 points x 5 components, has fewer than 2^31 elements)
+  int base;         // element offset of the line's first point (component 0)
+  int estride;      // element stride between consecutive points of the line
+  int line0 = 0;    // x-lines: first line of the block (line = z * ny + y)
+  int o = 0, kx0 = 0;
   bool active;
   if constexpr (XL) {
-    line0 = tile * W;
-    const long line = line0 + col;
+    line0 = (int)tile * W;
+    const int line = line0 + col;
     active = line < a.nlines;
-    base = (active ? line : 0) * (long)N * 5;
+    base = (active ? line : 0) * N * 5;
     estride = 5;
   } else {
-    const long ncolblk = (a.ncols + W - 1) / W;
-    o = tile / ncolblk;
-    kx0 = (tile % ncolblk) * W;
-    const long kx = kx0 + col;
+    const int ncolblk = ((int)a.ncols + W - 1) / W;
+    o = (int)tile / ncolblk;
+    kx0 = ((int)tile % ncolblk) * W;
+    const int kx = kx0 + col;
     active = kx < a.ncols;
-    base = o * a.outer_stride + (active ? kx : 0) * 5;
-    estride = a.stride;
+    base = o * (int)a.outer_stride + (active ? kx : 0) * 5;
+    estride = (int)a.stride;
   }
 
-  // unconditional loads (an inactive thread's base is a valid line), then masked
   cx<T> v[1][E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
-    v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
+    v[0][m] = active ? psi[base + (t + TL * m) * estride + c] : mk<T>(T(0), T(0));
 
   T* xre = lre + (col * 5 + c) * LS;
   T* xim = lim + (col * 5 + c) * LS;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
     if (a.store != nullptr && active) {
       cx<T>* st = reinterpret_cast<cx<T>*>(a.store);
 #pragma unroll
-      for (int m = 0; m < E; ++m) st[base + (long)(t + TL * m) * estride + c] = v[0][m];
+      for (int m = 0; m < E; ++m) st[base + (t + TL * m) * estride + c] = v[0][m];
     }
   }
   double gacc[NGRAD] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -225,7 +225,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         for (int cc = 0; cc < 5; ++cc) p[cc] = mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
         if constexpr (XADJ) {
           // forward input of this nonlinear substep at the point, from the store
-          const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + (line < a.nlines ? line : 0) * (long)N * 5 + j * 5;
+          const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + (line < a.nlines ? line : 0) * N * 5 + j * 5;
           cx<T> q[5];
 #pragma unroll
           for (int cc = 0; cc < 5; ++cc) q[cc] = fw[cc];
@@ -256,15 +256,15 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       const int nxx = (int)a.ncols;
       for (int pt = tid; pt < W * N; pt += NT) {
         const int pc = pt / N, kl = pt % N;
-        const long kx = kx0 + pc < a.ncols ? kx0 + pc : 0;
-        const int px = (int)(kx < nxx / 2 ? kx : kx - nxx);
+        const int kx = kx0 + pc < nxx ? kx0 + pc : 0;
+        const int px = kx < nxx / 2 ? kx : kx - nxx;
         const T nup = T(px * a.nu_scale_a);
         int kq;
-        long qidx;
+        int qidx;
         cx<T> ka = kin_a[kx];
         if (a.dim == 2) {
           kq = kl;
-          qidx = (long)kl * nxx + kx;
+          qidx = kl * nxx + kx;
         } else {
           kq = (int)o;
           qidx = o * nxx + kx;
@@ -288,7 +288,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
           sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
           if (kx0 + pc < a.ncols) {
             // m_a = -d Im(L^H f_a H), L = P^H L'/N^d (p), H the stored forward input
-            const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + o * a.outer_stride + kx * 5 + (long)kl * a.stride;
+            const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + o * (int)a.outer_stride + kx * 5 + kl * (int)a.stride;
             const double w4[4] = {1.0, 1.22474487139158904909864203735294570, 1.22474487139158904909864203735294570, 1.0};
             double upr = 0, upi = 0, umr = 0, umi = 0, uzi = 0;
             cx<T> hq[5];
@@ -362,7 +362,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
 
   if (active) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) psi[base + (long)(t + TL * m) * estride + c] = v[0][m];
+    for (int m = 0; m < E; ++m) psi[base + (t + TL * m) * estride + c] = v[0][m];
   }
   if constexpr (XL && !ADJ && PW) {
     if (a.clock_mode == CLOCK_ARG && tile == 0 && tid == 0) {

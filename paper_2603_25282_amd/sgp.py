@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsgp.so")
 
 SGP_OK = 0
 SGP_C64, SGP_C128 = 0, 1
-SGP_TS2, SGP_TS4 = 2, 4
+SGP_TS2, SGP_TS4, SGP_TS6 = 2, 4, 6
 SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
 SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
 SGP_TIME_IN_STEP = 256

@@ -33,7 +33,7 @@ def gpu_adjoint(psi0, gT, L, params, order, tau, n, K, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
-@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("order", [2, 4, 6])
 def test_adjoint_matches_oracle_adjoint(dtype, order):
     params = (60.0, -2.0, 3.0, 0.7, 0.9, 1.0, 1.2, 1.0)
     L, shape = 6.0, (32, 32)

@@ -215,3 +215,20 @@ def test_observed_temporal_orders_rotating_anisotropic():
             e.append(np.linalg.norm(u - ref))
         rate = np.log2(e[0] / e[1])
         assert abs(rate - want) < 0.15, (order, rate)
+
+
+def test_sixth_order_composition_observed_order():
+    # The triple jump S4(z1) S4(z0) S4(z1) (Yoshida's construction, which Sec. 3.3
+    # cites for higher orders) converges at order 6; its coefficients sum to 1 on
+    # both flows.
+    cfg = I.with_(I.C2, shape=(64, 64), name="order6")
+    psi0 = I.initial_state(cfg)
+    T = 0.05
+    ref = oracle.evolve(psi0, cfg.L, cfg.params, 6, T / 320, 320)
+    errs = []
+    for k in (5, 10, 20, 40):
+        got = oracle.evolve(psi0, cfg.L, cfg.params, 6, T / k, k)
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    print("TS6 errors", errs, "orders", rates)
+    assert all(5.5 < r < 6.3 for r in rates) and rates[-1] > 5.85
