@@ -272,6 +272,34 @@ def bench_ensemble(a):
     el = time.perf_counter() - t0
     gps = npts * steps / el
     finite = all(bool(torch.isfinite(torch.view_as_real(p)).all().item()) for p in psis)
+    adj = None
+    if a.adjoint_steps > 0:
+        # batched fwd + adjoint through autograd.ensemble_evolve (checkpoints every K)
+        from paper_2603_25282_amd.autograd import ensemble_evolve
+        n_adj = a.adjoint_steps
+        p0 = [p.detach().clone().requires_grad_(True) for p in psis]
+        par = torch.tensor([[c.params[i] for i in (4, 3, 0, 1, 2)] for c in insts], dtype=torch.float64,
+                           requires_grad=True)
+        gdir = [torch.randn(p.shape, dtype=p.dtype, device=p.device) for p in psis]
+
+        def fwd_bwd():
+            outs = ensemble_evolve(ens, p0, par, insts[0].tau, n_adj, K=a.K)
+            sum(torch.sum((torch.conj(g) * o).real) for g, o in zip(gdir, outs)).backward()
+
+        fwd_bwd()
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            for p in p0:
+                p.grad = None
+            par.grad = None
+            t0 = time.perf_counter()
+            fwd_bwd()
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        ta = sorted(runs)[1]
+        adj = {"metric": "5-comp grid-point-steps/s fwd+adjoint (batched ensemble)", "value": npts * n_adj / ta,
+               "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj, "median_of": 3}
     bpp = 80 + 88  # TS2: one X-pass and one Y-pass per step (state read + write, table entry)
     print(json.dumps({
         "metric": "5-comp grid-point-steps/s ensemble (96 2D grids, TS2)", "value": gps, "unit": "gp-steps/s",
@@ -280,7 +308,7 @@ def bench_ensemble(a):
         "data": "synthetic (seeded random-phase Gaussians, seeded parameters)",
         "config": {"workload": "ensemble-96", "grids": "32x128^2 + 48x256^2 + 16x384^2", "points": npts,
                    "L": insts[0].L, "scheme": "TS2", "tau": insts[0].tau, "plans": ens.plans(), "finite": finite},
-        "bytes_model": {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9}}), flush=True)
+        "bytes_model": {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9}, "fwd_adjoint": adj}), flush=True)
 
 
 class UnfusedFP64:

@@ -271,6 +271,31 @@ int sgp_ensemble_set_plan(sgp_ensemble* ens, int n, int axis, int elems);
 int sgp_ensemble_get_plan(const sgp_ensemble* ens, int n, int axis, int* elems);
 int sgp_ensemble_autotune(sgp_ensemble* ens, void* const* psi_devs, int steps, double* ms_per_step);
 
+/* Ensemble adjoint (the batched counterpart of sgp_step_store /
+ * sgp_adjoint_segment / sgp_adjoint_gradients): the same passes, one batched
+ * launch per pass type and plan width over all instances.
+ * sgp_ensemble_store_size: bytes of the caller's store for nsteps steps (one
+ *   argument block per launch, then every instance's 2M+1 stored states).
+ * sgp_ensemble_step_store: forward nsteps from the ensemble clock, storing every
+ *   pass's pointwise-stage input (store: device, 256-byte aligned); advances the
+ *   clock.
+ * sgp_ensemble_adjoint_segment: with the clock set back to the start of the
+ *   matching sgp_ensemble_step_store call (sgp_ensemble_set_time), replaces each
+ *   lam_devs[i] (gradient w.r.t. that call's output, 2 dJ/d conj(Phi)) by the
+ *   gradient w.r.t. its input, and adds each instance's parameter partials to its
+ *   accumulators.  It rewrites the argument block at the front of the store.
+ * sgp_ensemble_adjoint_gradients: out[5 i + q] = dJ/d(gamma, Omega, c0, c1, c2)[q]
+ *   of instance i accumulated since the last reset; reset = 1 clears.  Synchronous.
+ * Rotating frame only (as for contexts). */
+int sgp_ensemble_store_size(const sgp_ensemble* ens, long nsteps, size_t* bytes);
+int sgp_ensemble_step_store(sgp_ensemble* ens, void* const* psi_devs, long nsteps, void* store, size_t store_bytes);
+int sgp_ensemble_adjoint_segment(sgp_ensemble* ens, void* const* lam_devs, long nsteps, void* store,
+                                 size_t store_bytes);
+int sgp_ensemble_adjoint_gradients(sgp_ensemble* ens, double* out, int reset);
+/* Ensemble clock (all instances share it). */
+int sgp_ensemble_get_time(const sgp_ensemble* ens, double* t);
+int sgp_ensemble_set_time(sgp_ensemble* ens, double t);
+
 void sgp_ensemble_destroy(sgp_ensemble* ens);
 const char* sgp_ensemble_last_error(const sgp_ensemble* ens);
 

@@ -74,3 +74,51 @@ def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0, pla
     plan = plan if plan is None or plan == "auto" else tuple(int(e) for e in plan)
     return _Evolve.apply(psi0, params, tuple(shape), L, tuple(trap), float(tau), int(nsteps), int(order), int(K),
                          float(t0), plan)
+
+
+class _EnsembleEvolve(torch.autograd.Function):
+    """Differentiable batched ensemble evolution: inputs (ens, meta, params, *psis)."""
+
+    @staticmethod
+    def forward(ctx, ens, meta, params, *psis):
+        tau, nsteps, K, t0 = meta
+        states = [p.detach().clone().contiguous() for p in psis]
+        ckpts = []
+        for n0 in range(0, nsteps, K):
+            ckpts.append([p.clone() for p in states])
+            ens.time = t0 + n0 * tau
+            ens.step(states, min(K, nsteps - n0))
+        ctx.ens, ctx.ckpts, ctx.meta = ens, ckpts, meta
+        return tuple(states)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        ens, ckpts = ctx.ens, ctx.ckpts
+        tau, nsteps, K, t0 = ctx.meta
+        lams = [g.detach().to(ckpts[0][i].dtype).clone().contiguous() for i, g in enumerate(grads)]
+        ens.adjoint_gradients(reset=True)
+        store = None
+        for seg in range(len(ckpts) - 1, -1, -1):
+            n0 = seg * K
+            ns = min(K, nsteps - n0)
+            nbytes = ens.store_size(ns)
+            if store is None or store.numel() < nbytes:
+                store = torch.empty(nbytes, dtype=torch.uint8, device=lams[0].device)
+            states = [p.clone() for p in ckpts[seg]]
+            ens.time = t0 + n0 * tau
+            ens.step_store(states, ns, store)
+            ens.time = t0 + n0 * tau
+            ens.adjoint_segment(lams, ns, store)
+        dpar = torch.tensor(ens.adjoint_gradients(reset=True), dtype=torch.float64)
+        return (None, None, dpar) + tuple(lams)
+
+
+def ensemble_evolve(ens, psis, params, tau, nsteps, K=50, t0=0.0):
+    """Differentiable evolution of a batched Ensemble (its propagator built for tau):
+    psis a list of device states, params an (n_inst, 5) FP64 tensor of
+    (gamma, Omega, c0, c1, c2) equal to the ensemble's instance parameters (it carries
+    their gradients).  Returns the list of final states; gradients flow to every
+    psis[i] and to params through one batched adjoint per checkpoint segment."""
+    if not isinstance(params, torch.Tensor):
+        params = torch.tensor(params, dtype=torch.float64)
+    return list(_EnsembleEvolve.apply(ens, (float(tau), int(nsteps), int(K), float(t0)), params, *psis))

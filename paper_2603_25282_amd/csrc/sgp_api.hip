@@ -1247,6 +1247,130 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
   return SGP_OK;
 }
 
+// ---- ensemble adjoint: forward with stores and reverse sweep, batched ----------
+// The caller's store buffer holds, 256-byte aligned: one PassArgs per instance for
+// each of the 2M+1 launches of a call (M linear substeps), then each instance's
+// store of 2M+1 states (as sgp_step_store: slot 2k the input of the k-th nonlinear
+// substep, slot 2k+1 the Fourier-space input of the k-th propagator).
+size_t ens_args_bytes(const sgp_ensemble* e, long M) { return align256(sizeof(PassArgs) * (2 * M + 1) * e->n); }
+
+size_t ens_inst_store(const sgp_ensemble* e, int i, long nsteps) {
+  size_t b = 0;
+  sgp_store_size(e->ctx[i], nsteps, &b);
+  return align256(b);
+}
+
+PassArgs ens_xargs(sgp_ctx* c, void* state, int kind, double d, double s, void* store, const void* fwd) {
+  PassArgs a = base_args(c);
+  a.state = state;
+  a.n_line = c->g.n[0];
+  a.tw_fwd = c->at(c->off_tw[0][0]);
+  a.tw_inv = c->at(c->off_tw[0][1]);
+  a.d = d;
+  a.s_arg = s;
+  a.clock_mode = CLOCK_ARG;
+  a.store = store;
+  a.fwd = fwd;
+  a.gacc = (double*)c->at(c->off_gacc);
+  (void)kind;
+  return a;
+}
+
+PassArgs ens_cargs(sgp_ctx* c, void* state, int kind, int table, double d, void* store, const void* fwd) {
+  PassArgs a = base_args(c);
+  column_geometry(c, 1, a);
+  a.state = state;
+  a.n_line = c->g.n[1];
+  a.cs = c->at(c->off_cs[table]);
+  a.kin_a = c->at(c->off_kin[table][0]);
+  a.kin_o = c->at(c->off_kin[table][1]);
+  a.kin_l = c->at(c->off_kin[table][1]);
+  a.d = d;
+  a.advance_clock = kind == C_PROP ? 1 : 0;
+  a.store = store;
+  a.fwd = fwd;
+  a.gacc = (double*)c->at(c->off_gacc);
+  return a;
+}
+
+// Launch the batched pass `kind` for every instance with the args of launch L.
+template <typename T>
+hipError_t ens_launch_args(sgp_ensemble* e, int kind, const PassArgs* args_dev) {
+  const int ax = (kind == C_PROP || kind == C_ADJ) ? 1 : 0;
+  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
+  for (const auto& g : e->groups[ax]) {
+    hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args_dev, g.n, e->st);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+int ens_adjoint_run(sgp_ensemble* e, void* const* states, long nsteps, char* store, bool forward) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(e->ctx[0], nsteps, nl, lin, tab);
+  const long M = (long)lin.size();
+  std::vector<size_t> off(e->n);
+  size_t o = ens_args_bytes(e, M);
+  for (int i = 0; i < e->n; ++i) { off[i] = o; o += ens_inst_store(e, i, nsteps); }
+  std::vector<double> s(M + 1);
+  s[0] = e->t;
+  for (long k = 0; k < M; ++k) s[k + 1] = s[k] + lin[k];
+  // launch list: (kind, per-instance args)
+  std::vector<int> kinds;
+  std::vector<PassArgs> host;
+  host.reserve((size_t)(2 * M + 1) * e->n);
+  auto slot = [&](int i, long q) { return (void*)(store + off[i] + (size_t)q * e->ctx[i]->npts() * 5 * 2 * e->ctx[i]->esize); };
+  if (forward) {
+    for (long L = 0; L < 2 * M + 1; ++L) {
+      int kind;
+      if (L == 0) kind = X_FIRST;
+      else if (L % 2 == 1) kind = C_PROP;
+      else kind = (L == 2 * M) ? X_LAST : X_MID;
+      kinds.push_back(kind);
+      for (int i = 0; i < e->n; ++i) {
+        sgp_ctx* c = e->ctx[i];
+        if (kind == C_PROP) {
+          const long k = (L - 1) / 2;
+          host.push_back(ens_cargs(c, states[i], kind, tab[k], lin[k], slot(i, L), nullptr));
+        } else {
+          const long k = L / 2;  // nonlinear substep k at clock s[k]
+          host.push_back(ens_xargs(c, states[i], kind, nl[k], s[k], slot(i, L), nullptr));
+        }
+      }
+    }
+  } else {
+    for (long L = 2 * M; L >= 0; --L) {
+      int kind;
+      if (L == 2 * M) kind = XA_LAST;
+      else if (L % 2 == 1) kind = C_ADJ;
+      else kind = L == 0 ? XA_FIRST : XA_MID;
+      kinds.push_back(kind);
+      for (int i = 0; i < e->n; ++i) {
+        sgp_ctx* c = e->ctx[i];
+        if (kind == C_ADJ) {
+          const long k = (L - 1) / 2;
+          host.push_back(ens_cargs(c, states[i], kind, tab[k], lin[k], nullptr, slot(i, L)));
+        } else {
+          const long k = L / 2;
+          host.push_back(ens_xargs(c, states[i], kind, nl[k], s[k], nullptr, slot(i, L)));
+        }
+      }
+    }
+  }
+  hipError_t r = hipMemcpyAsync(store, host.data(), sizeof(PassArgs) * host.size(), hipMemcpyHostToDevice, e->st);
+  if (r == hipSuccess) r = hipStreamSynchronize(e->st);
+  if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "argument upload");
+  const PassArgs* args = (const PassArgs*)store;
+  for (size_t L = 0; L < kinds.size(); ++L) {
+    r = ens_launch_args<T>(e, kinds[L], args + L * e->n);
+    if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
+  }
+  if (forward) e->t += (double)nsteps * e->tau;
+  return SGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1455,6 +1579,67 @@ int sgp_ensemble_autotune(sgp_ensemble* e, void* const* psi_devs, int steps, dou
   e->t = t_save;
   if (rc == SGP_OK && ms_per_step) *ms_per_step = best;
   return rc;
+}
+
+int sgp_ensemble_store_size(const sgp_ensemble* e, long nsteps, size_t* bytes) {
+  if (!e || !bytes || nsteps < 1) return SGP_ERR_ARG;
+  if (e->scheme == 0) return SGP_ERR_STATE;
+  const long M = (long)(composition(e->scheme).A.size() - 1) * nsteps;
+  size_t b = ens_args_bytes(e, M);
+  for (int i = 0; i < e->n; ++i) b += ens_inst_store(e, i, nsteps);
+  *bytes = b;
+  return SGP_OK;
+}
+
+static int ens_adjoint_checks(sgp_ensemble* e, void* const* states, long nsteps, const void* store,
+                              size_t store_bytes) {
+  if (!e || !states || !store) return efail(e, SGP_ERR_ARG, "null argument");
+  if (nsteps < 1) return efail(e, SGP_ERR_ARG, "nsteps must be >= 1");
+  if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
+  if (e->scheme == 0) return efail(e, SGP_ERR_STATE, "propagator not built");
+  for (int i = 0; i < e->n; ++i)
+    if (!states[i]) return efail(e, SGP_ERR_ARG, "null state pointer");
+  if (((uintptr_t)store) & 255) return efail(e, SGP_ERR_ARG, "store must be 256-byte aligned");
+  size_t need = 0;
+  sgp_ensemble_store_size(e, nsteps, &need);
+  if (store_bytes < need) return efail(e, SGP_ERR_WORKSPACE, "store too small");
+  return SGP_OK;
+}
+
+int sgp_ensemble_step_store(sgp_ensemble* e, void* const* psi_devs, long nsteps, void* store, size_t store_bytes) {
+  int rc = ens_adjoint_checks(e, psi_devs, nsteps, store, store_bytes);
+  if (rc != SGP_OK) return rc;
+  return e->dtype == SGP_C64 ? ens_adjoint_run<float>(e, psi_devs, nsteps, (char*)store, true)
+                             : ens_adjoint_run<double>(e, psi_devs, nsteps, (char*)store, true);
+}
+
+int sgp_ensemble_adjoint_segment(sgp_ensemble* e, void* const* lam_devs, long nsteps, void* store,
+                                 size_t store_bytes) {
+  int rc = ens_adjoint_checks(e, lam_devs, nsteps, store, store_bytes);
+  if (rc != SGP_OK) return rc;
+  return e->dtype == SGP_C64 ? ens_adjoint_run<float>(e, lam_devs, nsteps, (char*)store, false)
+                             : ens_adjoint_run<double>(e, lam_devs, nsteps, (char*)store, false);
+}
+
+int sgp_ensemble_adjoint_gradients(sgp_ensemble* e, double* out, int reset) {
+  if (!e || !out) return efail(e, SGP_ERR_ARG, "null argument");
+  for (int i = 0; i < e->n; ++i) {
+    int rc = sgp_adjoint_gradients(e->ctx[i], out + 5 * (size_t)i, reset);
+    if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);
+  }
+  return SGP_OK;
+}
+
+int sgp_ensemble_get_time(const sgp_ensemble* e, double* t) {
+  if (!e || !t) return SGP_ERR_ARG;
+  *t = e->t;
+  return SGP_OK;
+}
+
+int sgp_ensemble_set_time(sgp_ensemble* e, double t) {
+  if (!e || !std::isfinite(t)) return SGP_ERR_ARG;
+  e->t = t;
+  return SGP_OK;
 }
 
 int sgp_ensemble_set_option(sgp_ensemble* e, int option, long value) {

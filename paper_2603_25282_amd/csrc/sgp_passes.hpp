@@ -356,7 +356,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
     if (tid < NGRAD) {
       double sum = 0.0;
       for (int wv = 0; wv < (NT + 63) / 64; ++wv) sum += gred[wv][tid];
-      a.gacc[(long)blockIdx.x * NGRAD + tid] += sum;
+      a.gacc[(long)tile * NGRAD + tid] += sum;  // one slot per tile of the instance
     }
   }
 
@@ -780,6 +780,10 @@ hipError_t launch_batched_e(int kind, const int2* it, const PassArgs* ar, long n
     case X_MID: hipLaunchKernelGGL((k_pass_batched<T, X_MID, E>), g, b, 0, st, it, ar); break;
     case X_LAST: hipLaunchKernelGGL((k_pass_batched<T, X_LAST, E>), g, b, 0, st, it, ar); break;
     case C_PROP: hipLaunchKernelGGL((k_pass_batched<T, C_PROP, E>), g, b, 0, st, it, ar); break;
+    case XA_FIRST: hipLaunchKernelGGL((k_pass_batched<T, XA_FIRST, E>), g, b, 0, st, it, ar); break;
+    case XA_MID: hipLaunchKernelGGL((k_pass_batched<T, XA_MID, E>), g, b, 0, st, it, ar); break;
+    case XA_LAST: hipLaunchKernelGGL((k_pass_batched<T, XA_LAST, E>), g, b, 0, st, it, ar); break;
+    case C_ADJ: hipLaunchKernelGGL((k_pass_batched<T, C_ADJ, E>), g, b, 0, st, it, ar); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -90,6 +90,8 @@ def exported_symbols():
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
             "sgp_ensemble_set_plan", "sgp_ensemble_get_plan", "sgp_ensemble_autotune",
+            "sgp_ensemble_store_size", "sgp_ensemble_step_store", "sgp_ensemble_adjoint_segment",
+            "sgp_ensemble_adjoint_gradients", "sgp_ensemble_get_time", "sgp_ensemble_set_time",
             "sgp_ensemble_last_error"]
 
 
@@ -339,6 +341,12 @@ class Ensemble:
         L.sgp_ensemble_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.sgp_ensemble_get_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.sgp_ensemble_autotune.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.sgp_ensemble_store_size.argtypes = [vp, ctypes.c_long, ctypes.POINTER(ctypes.c_size_t)]
+        L.sgp_ensemble_step_store.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_long, vp, ctypes.c_size_t]
+        L.sgp_ensemble_adjoint_segment.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_long, vp, ctypes.c_size_t]
+        L.sgp_ensemble_adjoint_gradients.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        L.sgp_ensemble_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.sgp_ensemble_set_time.argtypes = [vp, ctypes.c_double]
         L.sgp_ensemble_destroy.argtypes = [vp]
         L.sgp_ensemble_destroy.restype = None
         L.sgp_ensemble_last_error.argtypes = [vp]
@@ -383,6 +391,41 @@ class Ensemble:
 
     def set_option(self, option, value):
         self._chk(lib().sgp_ensemble_set_option(self._h, int(option), int(value)))
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        self._chk(lib().sgp_ensemble_get_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    @time.setter
+    def time(self, t):
+        self._chk(lib().sgp_ensemble_set_time(self._h, float(t)))
+
+    def _ptrs(self, psis):
+        for p, sh in zip(psis, self.shapes):
+            if p.dtype != self.torch_dtype or tuple(p.shape) != sh + (5,) or not p.is_contiguous():
+                raise SgpError("ensemble states must be contiguous (N, N, 5) tensors of the ensemble dtype")
+        return (ctypes.c_void_p * len(psis))(*[p.data_ptr() for p in psis])
+
+    def store_size(self, nsteps):
+        nb = ctypes.c_size_t()
+        self._chk(lib().sgp_ensemble_store_size(self._h, int(nsteps), ctypes.byref(nb)))
+        return int(nb.value)
+
+    def step_store(self, psis, nsteps, store):
+        self._chk(lib().sgp_ensemble_step_store(self._h, self._ptrs(psis), int(nsteps),
+                                                ctypes.c_void_p(store.data_ptr()), store.numel()))
+
+    def adjoint_segment(self, lams, nsteps, store):
+        self._chk(lib().sgp_ensemble_adjoint_segment(self._h, self._ptrs(lams), int(nsteps),
+                                                     ctypes.c_void_p(store.data_ptr()), store.numel()))
+
+    def adjoint_gradients(self, reset=True):
+        """(n_inst, 5) array: dJ/d(gamma, Omega, c0, c1, c2) per instance."""
+        out = (ctypes.c_double * (5 * len(self.shapes)))()
+        self._chk(lib().sgp_ensemble_adjoint_gradients(self._h, out, int(bool(reset))))
+        return np.array(out[:]).reshape(len(self.shapes), 5)
 
     def set_plan(self, n, axis, elems):
         """Plan width along axis (0 x, 1 y) of every instance of size n x n (0 = default)."""

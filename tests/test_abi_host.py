@@ -134,3 +134,33 @@ def test_ensemble_plan_setters_without_device():
     ptrs = (ctypes.c_void_p * 3)(1, 2, 3)
     assert L.sgp_ensemble_autotune(h, ptrs, 4, None) == -2  # no workspace
     L.sgp_ensemble_destroy(h)
+
+
+def test_ensemble_adjoint_entry_points_validate_without_device():
+    L = sgp.lib()
+    grids = (sgp._Grid * 1)()
+    pars = (sgp._Params * 1)()
+    grids[0].dim = 2
+    grids[0].n[0] = grids[0].n[1] = 64
+    grids[0].n[2] = 1
+    grids[0].L[0] = grids[0].L[1] = 8.0
+    pars[0] = sgp._Params(1, 1, 1, 0.5, 0.5, 1, 1, 1)
+    vp = ctypes.c_void_p
+    L.sgp_ensemble_create.argtypes = [ctypes.c_int, ctypes.POINTER(sgp._Grid), ctypes.POINTER(sgp._Params),
+                                      ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.sgp_ensemble_store_size.argtypes = [vp, ctypes.c_long, ctypes.POINTER(ctypes.c_size_t)]
+    L.sgp_ensemble_step_store.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_long, vp, ctypes.c_size_t]
+    L.sgp_ensemble_set_time.argtypes = [vp, ctypes.c_double]
+    L.sgp_ensemble_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.sgp_ensemble_destroy.argtypes = [vp]
+    L.sgp_ensemble_destroy.restype = None
+    h = vp()
+    assert L.sgp_ensemble_create(1, grids, pars, 1, None, ctypes.byref(h)) == 0
+    nb = ctypes.c_size_t()
+    assert L.sgp_ensemble_store_size(h, 4, ctypes.byref(nb)) == -2  # no scheme yet
+    ptrs = (vp * 1)(256)
+    assert L.sgp_ensemble_step_store(h, ptrs, 4, vp(256), 1 << 20) == -2  # no workspace
+    assert L.sgp_ensemble_set_time(h, 0.25) == 0
+    t = ctypes.c_double()
+    assert L.sgp_ensemble_get_time(h, ctypes.byref(t)) == 0 and t.value == 0.25
+    L.sgp_ensemble_destroy(h)
