@@ -199,7 +199,7 @@ __device__ __forceinline__ void lds_sync() {
 // NBUF: how many components share one LDS exchange round (1 <= NBUF <= NC); buffer
 // b of a line starts at b * lds_stride.
 template <typename T, int N, int E, int R, int NS, int SIGN, bool LAST, int NC, int NBUF, int SYNC>
-__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre, T* __restrict__ lim, int t,
+__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], cx<T>* __restrict__ lx, int t,
                                          const cx<T>* __restrict__ tw, int lds_stride) {
   constexpr int TL = N / E;
   constexpr int B = E / R;
@@ -243,8 +243,7 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre,
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int o = lds_pad(base + r * NS) + (c % NBUF) * lds_stride;
-          lre[o] = x[r].re;
-          lim[o] = x[r].im;
+          lx[o] = x[r];
         }
       }
     }
@@ -257,7 +256,7 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], T* __restrict__ lre,
 #pragma unroll
           for (int m = 0; m < E; ++m) {
             const int o = lds_pad(t + TL * m) + (cc % NBUF) * lds_stride;
-            v[cc][m] = mk<T>(lre[o], lim[o]);
+            v[cc][m] = lx[o];
           }
         lds_sync<SYNC>();
       }
@@ -333,31 +332,31 @@ __device__ __forceinline__ void stage_tw(cx<T>* __restrict__ dst, const void* __
 }
 
 template <typename T, int N, int E, int SIGN, int NS, int NC, int NBUF, int SYNC, int R, int... Rest>
-__device__ __forceinline__ void fft_passes(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[NC][E], cx<T>* lx, int t, const cx<T>* tw,
                                            int lds_stride) {
   constexpr bool last = sizeof...(Rest) == 0;
-  fft_pass<T, N, E, R, NS, SIGN, last, NC, NBUF, SYNC>(v, lre, lim, t, tw, lds_stride);
+  fft_pass<T, N, E, R, NS, SIGN, last, NC, NBUF, SYNC>(v, lx, t, tw, lds_stride);
   if constexpr (!last) {
-    fft_passes<T, N, E, SIGN, NS * R, NC, NBUF, SYNC, Rest...>(v, lre, lim, t,
+    fft_passes<T, N, E, SIGN, NS * R, NC, NBUF, SYNC, Rest...>(v, lx, t,
                                                               tw + (NS > 1 ? 2 * NS * (R - 1) : 0), lds_stride);
   }
 }
 
 template <typename T, int N, int E, int SIGN, int NC, int NBUF, int SYNC, int... Rs>
-__device__ __forceinline__ void fft_run(RadixList<Rs...>, cx<T> (&v)[NC][E], T* lre, T* lim, int t,
+__device__ __forceinline__ void fft_run(RadixList<Rs...>, cx<T> (&v)[NC][E], cx<T>* lx, int t,
                                         const cx<T>* tw, int lds_stride) {
-  fft_passes<T, N, E, SIGN, 1, NC, NBUF, SYNC, Rs...>(v, lre, lim, t, tw, lds_stride);
+  fft_passes<T, N, E, SIGN, 1, NC, NBUF, SYNC, Rs...>(v, lx, t, tw, lds_stride);
 }
 
 // Forward (SIGN = -1) or inverse (SIGN = +1) unscaled transform of NC components.
 // tw points at the table of the plan for this direction.
 template <typename T, int N, int E, int SIGN, int NC, int NBUF, int SYNC>
-__device__ __forceinline__ void fft_line(cx<T> (&v)[NC][E], T* lre, T* lim, int t, const cx<T>* tw,
+__device__ __forceinline__ void fft_line(cx<T> (&v)[NC][E], cx<T>* lx, int t, const cx<T>* tw,
                                          int lds_stride) {
   if constexpr (SIGN < 0)
-    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::fwd{}, v, lre, lim, t, tw, lds_stride);
+    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::fwd{}, v, lx, t, tw, lds_stride);
   else
-    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::inv{}, v, lre, lim, t, tw, lds_stride);
+    fft_run<T, N, E, SIGN, NC, NBUF, SYNC>(typename Plan<N, E>::inv{}, v, lx, t, tw, lds_stride);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,10 +27,11 @@ namespace sgp {
 
 // LDS line stride of the FFT exchanges: N + N/8 (one pad slot per 8) plus a per-length
 // extra that spreads the 5 component lines of adjacent lanes over the 32 banks
-// (chosen with a bank-conflict model of every exchange pattern).
+// (chosen with a bank-conflict model of every exchange pattern; complex values are
+// interleaved, one 8- or 16-byte LDS access each).
 template <int N> struct PadLine {
-  static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 3 : N == 64 ? 5 : N == 384 ? 25
-                             : N == 32 ? 1 : N == 16 ? 9 : 1;
+  static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 13 : N == 64 ? 5 : N == 384 ? 2
+                             : N == 32 ? 9 : N == 16 ? 1 : 1;
   static constexpr int size = N + N / 8 + extra;
 };
 
@@ -91,7 +92,7 @@ constexpr int pass_lds() {
 
 // Body of one block of a pass over `tile` (W lines), with caller-provided LDS.
 template <typename T, int N, int E, int W, int KIND>
-__device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArgs& a, long tile, T* lre, T* lim,
+__device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArgs& a, long tile, cx<T>* lx,
                                           cx<T>* ltw, double (*gred)[NGRAD]) {
   constexpr int TL = N / E;
   constexpr int NT = W * 5 * TL;
@@ -137,8 +138,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
   for (int m = 0; m < E; ++m)
     v[0][m] = active ? psi[base + (t + TL * m) * estride + c] : mk<T>(T(0), T(0));
 
-  T* xre = lre + (col * 5 + c) * LS;
-  T* xim = lim + (col * 5 + c) * LS;
+  cx<T>* xl = lx + (col * 5 + c) * LS;
   // twiddle tables staged in LDS while the state loads are in flight
   constexpr int TWF = KindInfo<KIND>::HF ? 2 * TwSize<N, E>::fwd : 0;
   constexpr int TWI = KindInfo<KIND>::HI ? 2 * TwSize<N, E>::inv : 0;
@@ -149,9 +149,9 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
 
   if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID ||
                 KIND == X_INV)
-    fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, twi, 0);
   if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || KIND == X_FWD || KindInfo<KIND>::SHEAR)
-    fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
+    fft_line<T, N, E, -1, 1, 1, 0>(v, xl, t, twf, 0);
 
   if constexpr (KindInfo<KIND>::SHEAR) {
     // f(.. + a w ..) along the line: coefficient k times exp(i nu_k a w) / N, w the
@@ -177,7 +177,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       const T vr = v[0][m].re, vi = v[0][m].im;
       v[0][m] = mk<T>(T(zr) * vr - T(zi) * vi, T(zr) * vi + T(zi) * vr);
     }
-    fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, twi, 0);
   }
 
   // forward store mode: keep the pointwise-stage input for the adjoint
@@ -195,8 +195,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int o5 = (col * N + t + TL * m) * 5 + c;
-      lre[o5] = v[0][m].re;
-      lim[o5] = v[0][m].im;
+      lx[o5] = v[0][m];
     }
     __syncthreads();
     if constexpr (XL) {
@@ -222,7 +221,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         const double V = 0.5 * (a.g2[0] * X * X + a.g2[1] * Y * Y + a.g2[2] * z * z);
         cx<T> p[5];
 #pragma unroll
-        for (int cc = 0; cc < 5; ++cc) p[cc] = mk<T>(lre[pt * 5 + cc], lim[pt * 5 + cc]);
+        for (int cc = 0; cc < 5; ++cc) p[cc] = lx[pt * 5 + cc];
         if constexpr (XADJ) {
           // forward input of this nonlinear substep at the point, from the store
           const cx<T>* fw = reinterpret_cast<const cx<T>*>(a.fwd) + (line < a.nlines ? line : 0) * N * 5 + j * 5;
@@ -243,7 +242,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
           nl_point<T>(p, V, K);
         }
 #pragma unroll
-        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+        for (int cc = 0; cc < 5; ++cc) lx[pt * 5 + cc] = p[cc];
       }
     } else {
       const T* cs = reinterpret_cast<const T*>(a.cs);
@@ -282,7 +281,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         cx<T> p[5];
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc)
-          p[cc] = mk<T>(kmul<T>(norm, norm_lo, lre[pt * 5 + cc]), kmul<T>(norm, norm_lo, lim[pt * 5 + cc]));
+          p[cc] = mk<T>(kmul<T>(norm, norm_lo, lx[pt * 5 + cc].re), kmul<T>(norm, norm_lo, lx[pt * 5 + cc].im));
         if constexpr (KIND == C_ADJ) {
           // P^H = P(-d): same (C - 1), S -> -S, conjugate kinetic phase
           sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
@@ -327,21 +326,21 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
           sym4_apply_inc<T>(as, beta, ss, p);
         }
 #pragma unroll
-        for (int cc = 0; cc < 5; ++cc) { lre[pt * 5 + cc] = p[cc].re; lim[pt * 5 + cc] = p[cc].im; }
+        for (int cc = 0; cc < 5; ++cc) lx[pt * 5 + cc] = p[cc];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int o5 = (col * N + t + TL * m) * 5 + c;
-      v[0][m] = mk<T>(lre[o5], lim[o5]);
+      v[0][m] = lx[o5];
     }
     __syncthreads();
   }
 
   if constexpr (KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST)
-    fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, twf, 0);
-  if constexpr (KIND == C_PROP || KIND == C_ADJ) fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, twi, 0);
+    fft_line<T, N, E, -1, 1, 1, 0>(v, xl, t, twf, 0);
+  if constexpr (KIND == C_PROP || KIND == C_ADJ) fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, twi, 0);
 
   if constexpr (ADJ) {
     // parameter partials: block reduction in a fixed order into this block's slot
@@ -390,11 +389,10 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_pass(cx<T>* __restrict__ ps
   constexpr int BUF = pass_lds<N, W, KIND>();
   constexpr int NT = W * 5 * (N / E);
   constexpr int TWB = (pass_tw<N, E, KIND>() * (int)sizeof(cx<T>) + 15) / 16;
-  __shared__ T lre[BUF];
-  __shared__ T lim[BUF];
+  __shared__ cx<T> lx[BUF];
   __shared__ uint4 ltw[TWB > 0 ? TWB : 1];
   __shared__ double gred[KindInfo<KIND>::ADJ ? NT / 64 + 1 : 1][NGRAD];
-  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lre, lim, reinterpret_cast<cx<T>*>(ltw),
+  pass_body<T, N, E, W, KIND>(psi, a, xcd_tile(blockIdx.x, gridDim.x), lx, reinterpret_cast<cx<T>*>(ltw),
                               gred);
 }
 
@@ -427,8 +425,7 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
                                 cmax(batched_tw<256, E, KIND, ES>(), batched_tw<384, E, KIND, ES>())),
                            batched_tw<512, E, KIND, ES>());
   constexpr int TWB = (TWM * (int)sizeof(cx<T>) + 15) / 16;
-  __shared__ T lre[BUF > 0 ? BUF : 1];
-  __shared__ T lim[BUF > 0 ? BUF : 1];
+  __shared__ cx<T> lx[BUF > 0 ? BUF : 1];
   __shared__ uint4 ltwr[TWB > 0 ? TWB : 1];
   cx<T>* ltw = reinterpret_cast<cx<T>*>(ltwr);
   __shared__ double gred[KindInfo<KIND>::ADJ ? 6 : 1][NGRAD];
@@ -438,7 +435,7 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
 #define SGP_BCASE(NN)                                                                                  \
   case NN:                                                                                             \
     if constexpr (batched_plan_ok(NN, E, ES))                                                          \
-      pass_body<T, NN, E, lines_per_block(NN, E), KIND>(psi, a, it.y, lre, lim, ltw, gred);             \
+      pass_body<T, NN, E, lines_per_block(NN, E), KIND>(psi, a, it.y, lx, ltw, gred);                   \
     break;
   switch (a.n_line) {
     SGP_BCASE(64) SGP_BCASE(128) SGP_BCASE(256) SGP_BCASE(384) SGP_BCASE(512)
@@ -472,8 +469,7 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
   constexpr int TILE = 2 * W * N * 5;
   constexpr int XCH = W * 5 * LS;
   constexpr int BUF = TILE > XCH ? TILE : XCH;
-  __shared__ T lre[BUF];
-  __shared__ T lim[BUF];
+  __shared__ cx<T> lx[BUF];
   __shared__ double red[NT / 64 + 1][NOBS];
 
   const int tid = threadIdx.x;
@@ -505,10 +501,9 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
     v[0][m] = active ? psi[base + (long)(t + TL * m) * estride + c] : mk<T>(T(0), T(0));
     f[m] = v[0][m];
   }
-  T* xre = lre + (col * 5 + c) * LS;
-  T* xim = lim + (col * 5 + c) * LS;
+  cx<T>* xl = lx + (col * 5 + c) * LS;
   // derivative along the line: FFT, multiply by i nu / N, inverse FFT
-  fft_line<T, N, E, -1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
+  fft_line<T, N, E, -1, 1, 1, 0>(v, xl, t, reinterpret_cast<const cx<T>*>(a.tw_fwd), 0);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + TL * m;
@@ -516,15 +511,13 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
     const T nu = T(p * a.nu_scale_l / N);
     v[0][m] = mk<T>(-nu * v[0][m].im, nu * v[0][m].re);
   }
-  fft_line<T, N, E, +1, 1, 1, 0>(v, xre, xim, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
+  fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, reinterpret_cast<const cx<T>*>(a.tw_inv), 0);
   // tile: psi at [0, W N 5), derivative at [W N 5, 2 W N 5)
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int o5 = (col * N + t + TL * m) * 5 + c;
-    lre[o5] = f[m].re;
-    lim[o5] = f[m].im;
-    lre[W * N * 5 + o5] = v[0][m].re;
-    lim[W * N * 5 + o5] = v[0][m].im;
+    lx[o5] = f[m];
+    lx[W * N * 5 + o5] = v[0][m];
   }
   __syncthreads();
   double acc[NOBS];
@@ -555,10 +548,10 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
     double pr[5], pi[5], dr[5], di[5];
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
-      pr[cc] = lre[pt * 5 + cc];
-      pi[cc] = lim[pt * 5 + cc];
-      dr[cc] = lre[W * N * 5 + pt * 5 + cc];
-      di[cc] = lim[W * N * 5 + pt * 5 + cc];
+      pr[cc] = lx[pt * 5 + cc].re;
+      pi[cc] = lx[pt * 5 + cc].im;
+      dr[cc] = lx[W * N * 5 + pt * 5 + cc].re;
+      di[cc] = lx[W * N * 5 + pt * 5 + cc].im;
     }
     double grad2 = 0.0, rot = 0.0;
 #pragma unroll
