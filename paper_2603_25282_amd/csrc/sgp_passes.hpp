@@ -261,12 +261,14 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         int kq;
         int qidx;
         cx<T> ka = kin_a[kx];
+        // table kx-major: a column block reads its entries contiguously (2D) or
+        // one broadcast entry (3D)
         if (a.dim == 2) {
           kq = kl;
-          qidx = kl * nxx + kx;
+          qidx = kx * a.n_q + kl;
         } else {
           kq = (int)o;
-          qidx = o * nxx + kx;
+          qidx = kx * a.n_q + o;
           const cx<T> ko = kin_o[o];
           ka = ka + ko + ka * ko;
         }
@@ -632,14 +634,15 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
 // exp(i d Q) is the spin-2 image of exp(i d n.sigma/2) = C + i S n.sigma with
 // C = cos(lam d/2), S = sin(lam d/2)/lam, lam = |n| = sqrt(Omega^2 + gamma^2
 // (nu_p^2 + nu_q^2)).  Stored per (p, q), rounded to T: (C - 1, S), with
-// C - 1 = -2 sin^2(lam d/4).  Kinetic tables per axis: exp(-i d nu^2/2) - 1.
+// C - 1 = -2 sin^2(lam d/4), at entry kx * ny + ky (kx-major, the order the
+// last-axis pass reads it in).  Kinetic tables per axis: exp(-i d nu^2/2) - 1.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_build_cs(T* __restrict__ cs, int nx, int ny, double Lx, double Ly, double Omega, double gamma,
                            double d) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)nx * ny) return;
-  const int kx = (int)(i % nx), ky = (int)(i / nx);
+  const int kx = (int)(i / ny), ky = (int)(i % ny);
   const int p = kx < nx / 2 ? kx : kx - nx;
   const int q = ky < ny / 2 ? ky : ky - ny;
   const double pi = 3.14159265358979323846264338327950288;
