@@ -6,8 +6,10 @@ adjoint split steps, with checkpointed recomputation every K steps.
 psi0: complex device tensor in the library layout (..., nx, 5); params: real tensor
 (gamma, Omega, c0, c1, c2).  Gradients follow torch's convention for complex tensors
 (2 dJ/d conj(psi)); the library's adjoint uses the same one.  Memory: the forward
-keeps ceil(nsteps/K) checkpoints; the backward holds one segment store of
-(2M + 1) states (M linear substeps of K steps) at a time.
+keeps a checkpoint at the start of every K-step segment and runs the last segment
+with stores (one segment store of (2M + 1) states, M linear substeps of K steps),
+which the first backward uses without recomputing that segment; the backward holds
+that one store at a time (a second backward recomputes every segment).
 """
 import math
 
@@ -35,12 +37,19 @@ class _Evolve(torch.autograd.Function):
         dtype = "complex64" if psi0.dtype == torch.complex64 else "complex128"
         s = _solver(shape, L, params.detach().cpu().tolist(), trap, dtype, tau, order, plan, psi0.detach())
         psi = psi0.detach().clone().contiguous()
-        ckpts = []
+        keep = any(ctx.needs_input_grad[:2])
+        ckpts, store = [], None
         for n0 in range(0, nsteps, K):
-            ckpts.append(psi.clone())
             s.time = t0 + n0 * tau
-            s.step(psi, min(K, nsteps - n0))
-        ctx.s, ctx.ckpts = s, ckpts
+            ns = min(K, nsteps - n0)
+            ckpts.append(psi.clone())
+            if keep and n0 + K >= nsteps:
+                # last segment: run it with stores, the backward's first input
+                store = torch.empty(s.store_size(ns), dtype=torch.uint8, device=psi.device)
+                s.step_store(psi, ns, store)
+            else:
+                s.step(psi, ns)
+        ctx.s, ctx.ckpts, ctx.store = s, ckpts, store
         ctx.meta = (tau, nsteps, K, t0)
         return psi
 
@@ -48,18 +57,22 @@ class _Evolve(torch.autograd.Function):
     def backward(ctx, grad_out):
         s, ckpts = ctx.s, ctx.ckpts
         tau, nsteps, K, t0 = ctx.meta
-        lam = grad_out.detach().to(ckpts[0].dtype).clone().contiguous()
+        lam = grad_out.detach().to(s.torch_dtype).clone().contiguous()
         s.adjoint_gradients(reset=True)
-        store = None
+        # the forward's store holds the last segment; it is overwritten below, so a
+        # second backward recomputes every segment
+        store, ctx.store = ctx.store, None
+        fresh = store is not None
         for seg in range(len(ckpts) - 1, -1, -1):
             n0 = seg * K
             ns = min(K, nsteps - n0)
-            nbytes = s.store_size(ns)
-            if store is None or store.numel() < nbytes:
-                store = torch.empty(nbytes, dtype=torch.uint8, device=lam.device)
-            psi = ckpts[seg].clone()
-            s.time = t0 + n0 * tau
-            s.step_store(psi, ns, store)
+            if not (fresh and seg == len(ckpts) - 1):  # recompute the segment with stores
+                nbytes = s.store_size(ns)
+                if store is None or store.numel() < nbytes:
+                    store = torch.empty(nbytes, dtype=torch.uint8, device=lam.device)
+                psi = ckpts[seg].clone()
+                s.time = t0 + n0 * tau
+                s.step_store(psi, ns, store)
             s.time = t0 + n0 * tau
             s.adjoint_segment(lam, ns, store)
         dpar = torch.tensor(s.adjoint_gradients(reset=True), dtype=torch.float64)
@@ -83,30 +96,41 @@ class _EnsembleEvolve(torch.autograd.Function):
     def forward(ctx, ens, meta, params, *psis):
         tau, nsteps, K, t0 = meta
         states = [p.detach().clone().contiguous() for p in psis]
-        ckpts = []
+        keep = any(ctx.needs_input_grad[2:])
+        ckpts, store = [], None
         for n0 in range(0, nsteps, K):
-            ckpts.append([p.clone() for p in states])
             ens.time = t0 + n0 * tau
-            ens.step(states, min(K, nsteps - n0))
-        ctx.ens, ctx.ckpts, ctx.meta = ens, ckpts, meta
+            ns = min(K, nsteps - n0)
+            ckpts.append([p.clone() for p in states])
+            if keep and n0 + K >= nsteps:
+                # last segment: run it with stores, the backward's first input
+                store = torch.empty(ens.store_size(ns), dtype=torch.uint8, device=states[0].device)
+                ens.step_store(states, ns, store)
+            else:
+                ens.step(states, ns)
+        ctx.ens, ctx.ckpts, ctx.store, ctx.meta = ens, ckpts, store, meta
         return tuple(states)
 
     @staticmethod
     def backward(ctx, *grads):
         ens, ckpts = ctx.ens, ctx.ckpts
         tau, nsteps, K, t0 = ctx.meta
-        lams = [g.detach().to(ckpts[0][i].dtype).clone().contiguous() for i, g in enumerate(grads)]
+        lams = [g.detach().to(ens.torch_dtype).clone().contiguous() for g in grads]
         ens.adjoint_gradients(reset=True)
-        store = None
+        # the forward's store holds the last segment; it is overwritten below, so a
+        # second backward recomputes every segment
+        store, ctx.store = ctx.store, None
+        fresh = store is not None
         for seg in range(len(ckpts) - 1, -1, -1):
             n0 = seg * K
             ns = min(K, nsteps - n0)
-            nbytes = ens.store_size(ns)
-            if store is None or store.numel() < nbytes:
-                store = torch.empty(nbytes, dtype=torch.uint8, device=lams[0].device)
-            states = [p.clone() for p in ckpts[seg]]
-            ens.time = t0 + n0 * tau
-            ens.step_store(states, ns, store)
+            if not (fresh and seg == len(ckpts) - 1):  # recompute the segment with stores
+                nbytes = ens.store_size(ns)
+                if store is None or store.numel() < nbytes:
+                    store = torch.empty(nbytes, dtype=torch.uint8, device=lams[0].device)
+                states = [p.clone() for p in ckpts[seg]]
+                ens.time = t0 + n0 * tau
+                ens.step_store(states, ns, store)
             ens.time = t0 + n0 * tau
             ens.adjoint_segment(lams, ns, store)
         dpar = torch.tensor(ens.adjoint_gradients(reset=True), dtype=torch.float64)

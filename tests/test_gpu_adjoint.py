@@ -155,3 +155,46 @@ def test_3d_adjoint_matches_oracle_adjoint(dtype, order):
     tol = 1e-11 if dtype == "complex128" else 5e-5
     assert eg <= tol
     assert np.all(ed <= (1e-10 if dtype == "complex128" else 2e-4))
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_evolve_keeps_last_segment_and_second_backward(dtype):
+    # evolve runs the last checkpoint segment with stores and the first backward uses
+    # them without recomputing it: the output equals plain steps in the same chunks
+    # bitwise, a second backward (recomputing every segment) gives bitwise the same
+    # gradients, and both match the oracle's discrete adjoint
+    import torch
+    from paper_2603_25282_amd.autograd import evolve
+    from paper_2603_25282_amd.sgp import Solver
+    cfg = I.with_(I.C5, shape=(64, 64), L=8.0)
+    psi0 = I.initial_state(I.with_(cfg, init="gauss_phase"))
+    prm = cfg.params
+    tau, n, K = 1e-3, 7, 3
+    tdt = torch.complex64 if dtype == "complex64" else torch.complex128
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(21)
+    w = rng.standard_normal(psi0.shape) + 1j * rng.standard_normal(psi0.shape)
+    print(f"case evolve last-segment store {dtype}", flush=True)
+    p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(tdt).to(dev).requires_grad_(True)
+    par = torch.tensor([prm[i] for i in PIDX], dtype=torch.float64, requires_grad=True)
+    out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], tau, n, order=4, K=K)
+    s = Solver(cfg.shape, cfg.L, prm, dtype=dtype)
+    s.build_propagator(tau, 4)
+    q = p0.detach().clone()
+    for ns in (3, 3, 1):
+        s.step(q, ns)
+    torch.cuda.synchronize()
+    assert torch.equal(out.detach(), q)
+    g = torch.from_numpy(Solver.to_device_layout(w)).to(tdt).to(dev)
+    J = torch.sum((torch.conj(g) * out).real)
+    J.backward(retain_graph=True)
+    g1, d1 = p0.grad.clone(), par.grad.clone()
+    p0.grad, par.grad = None, None
+    J.backward()
+    assert torch.equal(p0.grad, g1) and torch.equal(par.grad, d1)
+    g_ref, d_ref = oracle.adjoint(psi0, w, cfg.L, prm, 4, tau, n, K=K)
+    eg = rel_l2(Solver.from_device_layout(g1.cpu().numpy().astype(np.complex128)), g_ref)
+    ed = np.abs(d1.numpy() - d_ref) / np.maximum(1.0, np.abs(d_ref))
+    print(f"  state grad {eg:.3e}, params {ed}", flush=True)
+    assert eg <= (1e-11 if dtype == "complex128" else 5e-5)
+    assert np.all(ed <= (1e-10 if dtype == "complex128" else 2e-4))
