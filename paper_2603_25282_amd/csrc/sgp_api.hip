@@ -1076,6 +1076,11 @@ struct sgp_ensemble {
   bool use_graph = true;
   bool batched = true;
   hipStream_t cap = nullptr;
+  // side streams and events of the fork/join that runs the width groups of one pass
+  // concurrently (they touch different instances)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
   hipGraphExec_t gexec = nullptr;
   int gsteps = 0;
   int scheme = 0;
@@ -1150,18 +1155,51 @@ hipError_t ens_upload_args(sgp_ensemble* e) {
   return r;
 }
 
+// One batched pass over every instance: one launch per plan-width group along
+// axis ax.  With several groups the launches go to separate streams between a fork
+// and a join event on st (parallel branches when st is being captured), so a group
+// with few tiles overlaps the others instead of running alone at its tail.
+template <typename T>
+hipError_t ens_launch_groups(sgp_ensemble* e, hipStream_t st, int kind, int ax, const PassArgs* args) {
+  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
+  const auto& gs = e->groups[ax];
+  if (gs.size() <= 1) {
+    for (const auto& g : gs) {
+      hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args, g.n, st);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  const size_t ns = gs.size() - 1;
+  hipError_t r = hipSuccess;
+  if (!e->ev_fork) r = hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming);
+  while (r == hipSuccess && e->side.size() < ns) {
+    hipStream_t sst = nullptr;
+    r = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking);
+    if (r == hipSuccess) e->side.push_back(sst);
+  }
+  while (r == hipSuccess && e->ev_join.size() < ns) {
+    hipEvent_t ev = nullptr;
+    r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (r == hipSuccess) e->ev_join.push_back(ev);
+  }
+  if (r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
+  for (size_t i = 0; i < ns && r == hipSuccess; ++i) r = hipStreamWaitEvent(e->side[i], e->ev_fork, 0);
+  for (size_t i = 0; i < gs.size() && r == hipSuccess; ++i)
+    r = launch_pass_batched<T>(kind, gs[i].e, items + gs[i].off, args, gs[i].n, i == 0 ? st : e->side[i - 1]);
+  for (size_t i = 0; i < ns && r == hipSuccess; ++i) {
+    r = hipEventRecord(e->ev_join[i], e->side[i]);
+    if (r == hipSuccess) r = hipStreamWaitEvent(st, e->ev_join[i], 0);
+  }
+  return r;
+}
+
 template <typename T>
 hipError_t ens_launch(sgp_ensemble* e, hipStream_t st, int slot) {
   const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
   const bool xl = slot <= ES_XLAST;
   const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
-  const int ax = xl ? 0 : 1;
-  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
-  for (const auto& g : e->groups[ax]) {
-    hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args, g.n, st);
-    if (r != hipSuccess) return r;
-  }
-  return hipSuccess;
+  return ens_launch_groups<T>(e, st, kind, xl ? 0 : 1, args);
 }
 
 // Tiles of an instance along one axis for plan width w (2D: N lines either way).
@@ -1296,13 +1334,7 @@ PassArgs ens_cargs(sgp_ctx* c, void* state, int kind, int table, double d, void*
 // Launch the batched pass `kind` for every instance with the args of launch L.
 template <typename T>
 hipError_t ens_launch_args(sgp_ensemble* e, int kind, const PassArgs* args_dev) {
-  const int ax = (kind == C_PROP || kind == C_ADJ) ? 1 : 0;
-  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
-  for (const auto& g : e->groups[ax]) {
-    hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args_dev, g.n, e->st);
-    if (r != hipSuccess) return r;
-  }
-  return hipSuccess;
+  return ens_launch_groups<T>(e, e->st, kind, (kind == C_PROP || kind == C_ADJ) ? 1 : 0, args_dev);
 }
 
 template <typename T>
@@ -1653,6 +1685,9 @@ void sgp_ensemble_destroy(sgp_ensemble* e) {
   if (!e) return;
   drop_egraph(e);
   if (e->cap) hipStreamDestroy(e->cap);
+  for (hipStream_t sst : e->side) hipStreamDestroy(sst);
+  for (hipEvent_t ev : e->ev_join) hipEventDestroy(ev);
+  if (e->ev_fork) hipEventDestroy(e->ev_fork);
   for (auto* c : e->ctx) sgp_destroy(c);
   delete e;
 }
