@@ -1069,6 +1069,10 @@ struct sgp_ensemble {
   struct Group { int e; long off; long n; };
   size_t off_items[2] = {0, 0}, off_args = 0;
   std::vector<Group> groups[2];
+  // partitions: the instances sharing an (x, y) plan-width pair, contiguous in both
+  // work lists; a forward step runs each partition's launches on its own stream
+  struct Part { int ex, ey; long off[2], n[2]; };
+  std::vector<Part> parts;
   char* ws = nullptr;
   int nslots = 0;  // PassArgs slots (per instance): see ens_slots()
   std::vector<void*> psis;
@@ -1155,6 +1159,23 @@ hipError_t ens_upload_args(sgp_ensemble* e) {
   return r;
 }
 
+// Make sure n side streams and join events (and the fork event) exist.
+hipError_t ens_side_streams(sgp_ensemble* e, size_t n) {
+  hipError_t r = hipSuccess;
+  if (!e->ev_fork) r = hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming);
+  while (r == hipSuccess && e->side.size() < n) {
+    hipStream_t sst = nullptr;
+    r = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking);
+    if (r == hipSuccess) e->side.push_back(sst);
+  }
+  while (r == hipSuccess && e->ev_join.size() < n) {
+    hipEvent_t ev = nullptr;
+    r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (r == hipSuccess) e->ev_join.push_back(ev);
+  }
+  return r;
+}
+
 // One batched pass over every instance: one launch per plan-width group along
 // axis ax.  With several groups the launches go to separate streams between a fork
 // and a join event on st (parallel branches when st is being captured), so a group
@@ -1171,18 +1192,7 @@ hipError_t ens_launch_groups(sgp_ensemble* e, hipStream_t st, int kind, int ax, 
     return hipSuccess;
   }
   const size_t ns = gs.size() - 1;
-  hipError_t r = hipSuccess;
-  if (!e->ev_fork) r = hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming);
-  while (r == hipSuccess && e->side.size() < ns) {
-    hipStream_t sst = nullptr;
-    r = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking);
-    if (r == hipSuccess) e->side.push_back(sst);
-  }
-  while (r == hipSuccess && e->ev_join.size() < ns) {
-    hipEvent_t ev = nullptr;
-    r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (r == hipSuccess) e->ev_join.push_back(ev);
-  }
+  hipError_t r = ens_side_streams(e, ns);
   if (r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
   for (size_t i = 0; i < ns && r == hipSuccess; ++i) r = hipStreamWaitEvent(e->side[i], e->ev_fork, 0);
   for (size_t i = 0; i < gs.size() && r == hipSuccess; ++i)
@@ -1194,44 +1204,85 @@ hipError_t ens_launch_groups(sgp_ensemble* e, hipStream_t st, int kind, int ax, 
   return r;
 }
 
-template <typename T>
-hipError_t ens_launch(sgp_ensemble* e, hipStream_t st, int slot) {
-  const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
-  const bool xl = slot <= ES_XLAST;
-  const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
-  return ens_launch_groups<T>(e, st, kind, xl ? 0 : 1, args);
-}
-
 // Tiles of an instance along one axis for plan width w (2D: N lines either way).
 long ens_tiles(int N, int w) {
   const int W = lines_per_block(N, w);
   return (N + W - 1) / W;
 }
 
-// Rebuild and upload the work lists for the instances' current plans.
+// Rebuild and upload the work lists for the instances' current plans.  The x list
+// is ordered by (x width, y width, instance) and the y list by (y width, x width,
+// instance), so the instances of one width along an axis (a group) and of one
+// width pair (a partition) are contiguous in both lists.
 hipError_t ens_build_items(sgp_ensemble* e) {
+  std::vector<std::pair<int, int>> pairs;
+  for (auto* c : e->ctx) {
+    const std::pair<int, int> wp(c->plan_e[0], c->plan_e[1]);
+    if (std::find(pairs.begin(), pairs.end(), wp) == pairs.end()) pairs.push_back(wp);
+  }
+  std::sort(pairs.begin(), pairs.end());
+  e->parts.clear();
+  for (const auto& wp : pairs) e->parts.push_back(sgp_ensemble::Part{wp.first, wp.second, {0, 0}, {0, 0}});
   for (int ax = 0; ax < 2; ++ax) {
-    std::vector<int> widths;
-    for (auto* c : e->ctx)
-      if (std::find(widths.begin(), widths.end(), c->plan_e[ax]) == widths.end()) widths.push_back(c->plan_e[ax]);
-    std::sort(widths.begin(), widths.end());
+    std::vector<size_t> order(e->parts.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      const auto& A = e->parts[a];
+      const auto& B = e->parts[b];
+      return ax == 0 ? std::make_pair(A.ex, A.ey) < std::make_pair(B.ex, B.ey)
+                     : std::make_pair(A.ey, A.ex) < std::make_pair(B.ey, B.ex);
+    });
     std::vector<int2> items;
     e->groups[ax].clear();
-    for (int w : widths) {
-      sgp_ensemble::Group g{w, (long)items.size(), 0};
+    for (size_t k : order) {
+      auto& P = e->parts[k];
+      const int w = ax == 0 ? P.ex : P.ey;
+      if (e->groups[ax].empty() || e->groups[ax].back().e != w)
+        e->groups[ax].push_back(sgp_ensemble::Group{w, (long)items.size(), 0});
+      P.off[ax] = (long)items.size();
       for (int i = 0; i < e->n; ++i) {
-        if (e->ctx[i]->plan_e[ax] != w) continue;
+        if (e->ctx[i]->plan_e[0] != P.ex || e->ctx[i]->plan_e[1] != P.ey) continue;
         const long nt = ens_tiles(e->ctx[i]->g.n[0], w);
         for (long t = 0; t < nt; ++t) items.push_back(make_int2(i, (int)t));
       }
-      g.n = (long)items.size() - g.off;
-      e->groups[ax].push_back(g);
+      P.n[ax] = (long)items.size() - P.off[ax];
+      e->groups[ax].back().n = (long)items.size() - e->groups[ax].back().off;
     }
     hipError_t r = hipMemcpyAsync(e->ws + e->off_items[ax], items.data(), sizeof(int2) * items.size(),
                                   hipMemcpyHostToDevice, e->st);
     if (r != hipSuccess) return r;
   }
   return hipStreamSynchronize(e->st);
+}
+
+// One slot's batched pass over the instances of partition P, on stream st.
+template <typename T>
+hipError_t ens_launch_part(sgp_ensemble* e, const sgp_ensemble::Part& P, hipStream_t st, int slot) {
+  const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
+  const bool xl = slot <= ES_XLAST;
+  const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
+  const int ax = xl ? 0 : 1;
+  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
+  return launch_pass_batched<T>(kind, ax == 0 ? P.ex : P.ey, items + P.off[ax], args, P.n[ax], st);
+}
+
+// Run the slot sequence `slots` (repeated `reps` times) for every partition, each on
+// its own stream between one fork and one join event on st.
+template <typename T>
+hipError_t ens_run_parts(sgp_ensemble* e, hipStream_t st, const std::vector<int>& slots, long reps) {
+  const size_t np = e->parts.size();
+  hipError_t r = np > 1 ? ens_side_streams(e, np - 1) : hipSuccess;
+  if (np > 1 && r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
+  for (size_t k = 1; k < np && r == hipSuccess; ++k) r = hipStreamWaitEvent(e->side[k - 1], e->ev_fork, 0);
+  for (long b = 0; b < reps && r == hipSuccess; ++b)
+    for (size_t k = 0; k < np && r == hipSuccess; ++k)
+      for (int sl : slots)
+        if (r == hipSuccess) r = ens_launch_part<T>(e, e->parts[k], k == 0 ? st : e->side[k - 1], sl);
+  for (size_t k = 1; k < np && r == hipSuccess; ++k) {
+    r = hipEventRecord(e->ev_join[k - 1], e->side[k - 1]);
+    if (r == hipSuccess) r = hipStreamWaitEvent(st, e->ev_join[k - 1], 0);
+  }
+  return r;
 }
 
 // Slots of one body step (after a merged nonlinear substep, ending with the next one)
@@ -1245,9 +1296,12 @@ std::vector<int> ens_tail(int scheme) {
   return {ES_LIN0, ES_XMID, ES_LIN1, ES_XMID, ES_LIN0, ES_XLAST};
 }
 
+// A forward call: every partition runs its own launch sequence on its own stream
+// (one fork and one join per phase: first pass, graph replays, rest), so passes of
+// different partitions overlap freely.
 template <typename T>
 int ens_step_impl(sgp_ensemble* e, long nsteps) {
-  hipError_t r = ens_launch<T>(e, e->st, ES_XFIRST);
+  hipError_t r = ens_run_parts<T>(e, e->st, {ES_XFIRST}, 1);
   if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
   long nbody = nsteps - 1;
   const int G = 16;
@@ -1256,12 +1310,12 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
       drop_egraph(e);
       if (!e->cap && (r = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking)) != hipSuccess)
         return efail(e, SGP_ERR_HIP, "stream create");
+      // side streams exist before the capture starts (no stream creation inside it)
+      if (e->parts.size() > 1 && (r = ens_side_streams(e, e->parts.size() - 1)) != hipSuccess)
+        return efail(e, SGP_ERR_HIP, "stream create");
       r = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
       if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "graph capture");
-      hipError_t r1 = hipSuccess;
-      for (int b = 0; b < G && r1 == hipSuccess; ++b)
-        for (int sl : ens_body(e->scheme))
-          if (r1 == hipSuccess) r1 = ens_launch<T>(e, e->cap, sl);
+      hipError_t r1 = ens_run_parts<T>(e, e->cap, ens_body(e->scheme), G);
       hipGraph_t g = nullptr;
       r = hipStreamEndCapture(e->cap, &g);
       if (r1 != hipSuccess || r != hipSuccess) {
@@ -1277,11 +1331,11 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
       if ((r = hipGraphLaunch(e->gexec, e->st)) != hipSuccess) return efail(e, SGP_ERR_HIP, "graph launch");
     nbody %= G;
   }
+  std::vector<int> rest;
   for (long b = 0; b < nbody; ++b)
-    for (int sl : ens_body(e->scheme))
-      if ((r = ens_launch<T>(e, e->st, sl)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
-  for (int sl : ens_tail(e->scheme))
-    if ((r = ens_launch<T>(e, e->st, sl)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
+    for (int sl : ens_body(e->scheme)) rest.push_back(sl);
+  for (int sl : ens_tail(e->scheme)) rest.push_back(sl);
+  if ((r = ens_run_parts<T>(e, e->st, rest, 1)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
   return SGP_OK;
 }
 
