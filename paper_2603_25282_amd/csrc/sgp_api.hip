@@ -1064,13 +1064,11 @@ struct sgp_ensemble {
   std::vector<sgp_ctx*> ctx;
   std::vector<size_t> ws_off;
   size_t total = 0;
-  // work lists per axis (0: x-lines, 1: columns), grouped by plan width: one
-  // batched launch per group
-  struct Group { int e; long off; long n; };
-  size_t off_items[2] = {0, 0}, off_args = 0;
-  std::vector<Group> groups[2];
+  // work lists per axis (0: x-lines, 1: columns) of (instance, tile) items, and
   // partitions: the instances sharing an (x, y) plan-width pair, contiguous in both
-  // work lists; a forward step runs each partition's launches on its own stream
+  // lists; each partition's launches run on their own stream (one batched launch
+  // per pass and partition)
+  size_t off_items[2] = {0, 0}, off_args = 0;
   struct Part { int ex, ey; long off[2], n[2]; };
   std::vector<Part> parts;
   char* ws = nullptr;
@@ -1176,44 +1174,14 @@ hipError_t ens_side_streams(sgp_ensemble* e, size_t n) {
   return r;
 }
 
-// One batched pass over every instance: one launch per plan-width group along
-// axis ax.  With several groups the launches go to separate streams between a fork
-// and a join event on st (parallel branches when st is being captured), so a group
-// with few tiles overlaps the others instead of running alone at its tail.
-template <typename T>
-hipError_t ens_launch_groups(sgp_ensemble* e, hipStream_t st, int kind, int ax, const PassArgs* args) {
-  const int2* items = (const int2*)(e->ws + e->off_items[ax]);
-  const auto& gs = e->groups[ax];
-  if (gs.size() <= 1) {
-    for (const auto& g : gs) {
-      hipError_t r = launch_pass_batched<T>(kind, g.e, items + g.off, args, g.n, st);
-      if (r != hipSuccess) return r;
-    }
-    return hipSuccess;
-  }
-  const size_t ns = gs.size() - 1;
-  hipError_t r = ens_side_streams(e, ns);
-  if (r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
-  for (size_t i = 0; i < ns && r == hipSuccess; ++i) r = hipStreamWaitEvent(e->side[i], e->ev_fork, 0);
-  for (size_t i = 0; i < gs.size() && r == hipSuccess; ++i)
-    r = launch_pass_batched<T>(kind, gs[i].e, items + gs[i].off, args, gs[i].n, i == 0 ? st : e->side[i - 1]);
-  for (size_t i = 0; i < ns && r == hipSuccess; ++i) {
-    r = hipEventRecord(e->ev_join[i], e->side[i]);
-    if (r == hipSuccess) r = hipStreamWaitEvent(st, e->ev_join[i], 0);
-  }
-  return r;
-}
-
 // Tiles of an instance along one axis for plan width w (2D: N lines either way).
 long ens_tiles(int N, int w) {
   const int W = lines_per_block(N, w);
   return (N + W - 1) / W;
 }
 
-// Rebuild and upload the work lists for the instances' current plans.  The x list
-// is ordered by (x width, y width, instance) and the y list by (y width, x width,
-// instance), so the instances of one width along an axis (a group) and of one
-// width pair (a partition) are contiguous in both lists.
+// Rebuild and upload the work lists for the instances' current plans, one
+// contiguous run of items per partition (width pair) in each list.
 hipError_t ens_build_items(sgp_ensemble* e) {
   std::vector<std::pair<int, int>> pairs;
   for (auto* c : e->ctx) {
@@ -1224,21 +1192,9 @@ hipError_t ens_build_items(sgp_ensemble* e) {
   e->parts.clear();
   for (const auto& wp : pairs) e->parts.push_back(sgp_ensemble::Part{wp.first, wp.second, {0, 0}, {0, 0}});
   for (int ax = 0; ax < 2; ++ax) {
-    std::vector<size_t> order(e->parts.size());
-    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-      const auto& A = e->parts[a];
-      const auto& B = e->parts[b];
-      return ax == 0 ? std::make_pair(A.ex, A.ey) < std::make_pair(B.ex, B.ey)
-                     : std::make_pair(A.ey, A.ex) < std::make_pair(B.ey, B.ex);
-    });
     std::vector<int2> items;
-    e->groups[ax].clear();
-    for (size_t k : order) {
-      auto& P = e->parts[k];
+    for (auto& P : e->parts) {
       const int w = ax == 0 ? P.ex : P.ey;
-      if (e->groups[ax].empty() || e->groups[ax].back().e != w)
-        e->groups[ax].push_back(sgp_ensemble::Group{w, (long)items.size(), 0});
       P.off[ax] = (long)items.size();
       for (int i = 0; i < e->n; ++i) {
         if (e->ctx[i]->plan_e[0] != P.ex || e->ctx[i]->plan_e[1] != P.ey) continue;
@@ -1246,7 +1202,6 @@ hipError_t ens_build_items(sgp_ensemble* e) {
         for (long t = 0; t < nt; ++t) items.push_back(make_int2(i, (int)t));
       }
       P.n[ax] = (long)items.size() - P.off[ax];
-      e->groups[ax].back().n = (long)items.size() - e->groups[ax].back().off;
     }
     hipError_t r = hipMemcpyAsync(e->ws + e->off_items[ax], items.data(), sizeof(int2) * items.size(),
                                   hipMemcpyHostToDevice, e->st);
@@ -1266,23 +1221,32 @@ hipError_t ens_launch_part(sgp_ensemble* e, const sgp_ensemble::Part& P, hipStre
   return launch_pass_batched<T>(kind, ax == 0 ? P.ex : P.ey, items + P.off[ax], args, P.n[ax], st);
 }
 
-// Run the slot sequence `slots` (repeated `reps` times) for every partition, each on
-// its own stream between one fork and one join event on st.
-template <typename T>
-hipError_t ens_run_parts(sgp_ensemble* e, hipStream_t st, const std::vector<int>& slots, long reps) {
+// Run fn(partition, stream) for every partition, each on its own stream, between one
+// fork and one join event on st (parallel branches when st is being captured).
+template <typename F>
+hipError_t ens_fork_run(sgp_ensemble* e, hipStream_t st, F&& fn) {
   const size_t np = e->parts.size();
   hipError_t r = np > 1 ? ens_side_streams(e, np - 1) : hipSuccess;
   if (np > 1 && r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
   for (size_t k = 1; k < np && r == hipSuccess; ++k) r = hipStreamWaitEvent(e->side[k - 1], e->ev_fork, 0);
-  for (long b = 0; b < reps && r == hipSuccess; ++b)
-    for (size_t k = 0; k < np && r == hipSuccess; ++k)
-      for (int sl : slots)
-        if (r == hipSuccess) r = ens_launch_part<T>(e, e->parts[k], k == 0 ? st : e->side[k - 1], sl);
+  for (size_t k = 0; k < np && r == hipSuccess; ++k) r = fn(e->parts[k], k == 0 ? st : e->side[k - 1]);
   for (size_t k = 1; k < np && r == hipSuccess; ++k) {
     r = hipEventRecord(e->ev_join[k - 1], e->side[k - 1]);
     if (r == hipSuccess) r = hipStreamWaitEvent(st, e->ev_join[k - 1], 0);
   }
   return r;
+}
+
+// The slot sequence `slots`, repeated `reps` times, for every partition.
+template <typename T>
+hipError_t ens_run_parts(sgp_ensemble* e, hipStream_t st, const std::vector<int>& slots, long reps) {
+  return ens_fork_run(e, st, [&](const sgp_ensemble::Part& P, hipStream_t sst) {
+    hipError_t r = hipSuccess;
+    for (long b = 0; b < reps && r == hipSuccess; ++b)
+      for (int sl : slots)
+        if (r == hipSuccess) r = ens_launch_part<T>(e, P, sst, sl);
+    return r;
+  });
 }
 
 // Slots of one body step (after a merged nonlinear substep, ending with the next one)
@@ -1385,12 +1349,6 @@ PassArgs ens_cargs(sgp_ctx* c, void* state, int kind, int table, double d, void*
   return a;
 }
 
-// Launch the batched pass `kind` for every instance with the args of launch L.
-template <typename T>
-hipError_t ens_launch_args(sgp_ensemble* e, int kind, const PassArgs* args_dev) {
-  return ens_launch_groups<T>(e, e->st, kind, (kind == C_PROP || kind == C_ADJ) ? 1 : 0, args_dev);
-}
-
 template <typename T>
 int ens_adjoint_run(sgp_ensemble* e, void* const* states, long nsteps, char* store, bool forward) {
   std::vector<double> nl, lin;
@@ -1448,11 +1406,18 @@ int ens_adjoint_run(sgp_ensemble* e, void* const* states, long nsteps, char* sto
   hipError_t r = hipMemcpyAsync(store, host.data(), sizeof(PassArgs) * host.size(), hipMemcpyHostToDevice, e->st);
   if (r == hipSuccess) r = hipStreamSynchronize(e->st);
   if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "argument upload");
+  // every partition runs the whole launch list on its own stream
   const PassArgs* args = (const PassArgs*)store;
-  for (size_t L = 0; L < kinds.size(); ++L) {
-    r = ens_launch_args<T>(e, kinds[L], args + L * e->n);
-    if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
-  }
+  r = ens_fork_run(e, e->st, [&](const sgp_ensemble::Part& P, hipStream_t sst) {
+    hipError_t rr = hipSuccess;
+    for (size_t L = 0; L < kinds.size() && rr == hipSuccess; ++L) {
+      const int ax = (kinds[L] == C_PROP || kinds[L] == C_ADJ) ? 1 : 0;
+      const int2* items = (const int2*)(e->ws + e->off_items[ax]);
+      rr = launch_pass_batched<T>(kinds[L], ax == 0 ? P.ex : P.ey, items + P.off[ax], args + L * e->n, P.n[ax], sst);
+    }
+    return rr;
+  });
+  if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
   if (forward) e->t += (double)nsteps * e->tau;
   return SGP_OK;
 }
