@@ -65,7 +65,7 @@ enum { SGP_TS2 = 2, SGP_TS4 = 4, SGP_TS6 = 6 };
 typedef struct sgp_ctx sgp_ctx;
 
 /* Grid: dim = 2 or 3; n[0..dim-1] = points along x, y[, z]; L[] = half-widths.
- * Supported n per axis: 16, 32, 64, 128, 256, 512. */
+ * Supported n per axis: 16, 32, 64, 128, 256, 512 and 192, 384, 768 (3 * 2^k). */
 typedef struct {
   int dim;
   int n[3];
@@ -175,10 +175,11 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
 /* Register plans of the FFT line kernels.  Every pass along an axis of length n
  * transforms each (line, component) with n/E threads holding E elements each; E
  * fixes the radix sequence (E = 8: radix 8 with one radix-2/4 pass; E = 4: radix 4
- * with one radix-2 pass; E = 16: radix 8 with two butterflies per thread; 384:
- * E = 12 {3,4,4,4,2} or, for SGP_C64 only, E = 24 {3,8,8,2}) and the block shape.  Every plan computes
- * the same transform (results differ by rounding only).  Defaults: E = 8, or 12
- * for 384.
+ * with one radix-2 pass; E = 16: radix 8 with two butterflies per thread; 192,
+ * 384, 768: E = 12 (radix 3 and radix 4, 384 with one radix 2) or, for SGP_C64
+ * only, E = 24 (radix 3 and radix 8, 384 with one radix 2, 768 with one radix 4))
+ * and the block shape.  Every plan computes the same transform (results differ by
+ * rounding only).  Defaults: E = 8, or 12 for 192, 384, 768.
  *
  * sgp_plan_widths: writes up to max_out widths available for length n and
  *   element type dtype (the default first) to out and returns how many there
@@ -233,7 +234,7 @@ void sgp_destroy(sgp_ctx* ctx);
 const char* sgp_last_error(const sgp_ctx* ctx);
 
 /* ---- Ensembles of 2D grids -------------------------------------------------
- * Many independent 2D instances (square grids with N in {64, 128, 256, 384, 512},
+ * Many independent 2D instances (square grids with N in {64, 128, 192, 256, 384, 512, 768},
  * each with its own domain and parameters, same element type and scheme) advanced
  * together: every pass type of a step is one batched launch (per register plan
  * width in use) over the work list of the instances' line tiles, and the periodic

@@ -29,7 +29,9 @@ std::vector<int> plan_of(bool fwd) {
   return fwd ? radix_list(typename Plan<N, E>::fwd{}) : radix_list(typename Plan<N, E>::inv{});
 }
 
-bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 384 || n == 512; }
+bool supported_n(int n) {
+  return n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512 || n == 768;
+}
 
 std::vector<int> plan_radices(int n, int e, bool fwd) {
 #define SGP_PLAN(NN, EE) \
@@ -37,7 +39,7 @@ std::vector<int> plan_radices(int n, int e, bool fwd) {
   SGP_PLAN(16, 4) SGP_PLAN(32, 4) SGP_PLAN(64, 4) SGP_PLAN(128, 4) SGP_PLAN(256, 4) SGP_PLAN(512, 4)
   SGP_PLAN(16, 8) SGP_PLAN(32, 8) SGP_PLAN(64, 8) SGP_PLAN(128, 8) SGP_PLAN(256, 8) SGP_PLAN(512, 8)
   SGP_PLAN(64, 16) SGP_PLAN(128, 16) SGP_PLAN(256, 16) SGP_PLAN(512, 16)
-  SGP_PLAN(384, 12) SGP_PLAN(384, 24)
+  SGP_PLAN(384, 12) SGP_PLAN(384, 24) SGP_PLAN(192, 12) SGP_PLAN(192, 24) SGP_PLAN(768, 12) SGP_PLAN(768, 24)
 #undef SGP_PLAN
   return {};
 }
@@ -775,7 +777,7 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
   for (int i = 0; i < grid->dim; ++i) {
     if (!supported_n(grid->n[i]))
       return fail(nullptr, SGP_ERR_ARG, "unsupported grid size " + std::to_string(grid->n[i]) +
-                                            " (supported: 16, 32, 64, 128, 256, 384, 512)");
+                                            " (supported: 16, 32, 64, 128, 192, 256, 384, 512, 768)");
     if (!(grid->L[i] > 0.0) || !std::isfinite(grid->L[i])) return fail(nullptr, SGP_ERR_ARG, "L must be > 0");
   }
   const double* pv = &params->c0;
@@ -1437,11 +1439,10 @@ int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* par
   e->st = (hipStream_t)hip_stream;
   size_t off = 0;
   for (int i = 0; i < n_inst; ++i) {
-    if (grids[i].dim != 2 || grids[i].n[0] != grids[i].n[1] ||
-        (grids[i].n[0] != 64 && grids[i].n[0] != 128 && grids[i].n[0] != 256 && grids[i].n[0] != 384 &&
-         grids[i].n[0] != 512)) {
+    if (grids[i].dim != 2 || grids[i].n[0] != grids[i].n[1] || grids[i].n[0] < 64 || !supported_n(grids[i].n[0])) {
       delete e;
-      return efail(nullptr, SGP_ERR_ARG, "ensemble grids must be 2D N x N with N in {64, 128, 256, 384, 512}");
+      return efail(nullptr, SGP_ERR_ARG,
+                   "ensemble grids must be 2D N x N with N in {64, 128, 192, 256, 384, 512, 768}");
     }
     sgp_ctx* c = nullptr;
     int rc = sgp_create(&grids[i], &params[i], dtype, hip_stream, &c);

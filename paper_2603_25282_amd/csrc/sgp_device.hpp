@@ -290,6 +290,11 @@ template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = R
 // 384 = 3 * 2^7: E = 12 (default) and E = 24
 template <> struct Plan<384, 12> { using fwd = RadixList<3, 4, 4, 4, 2>; using inv = RadixList<2, 4, 4, 4, 3>; };
 template <> struct Plan<384, 24> { using fwd = RadixList<3, 8, 8, 2>; using inv = RadixList<2, 8, 8, 3>; };
+// 192 = 3 * 2^6 and 768 = 3 * 2^8: E = 12 (default) and E = 24
+template <> struct Plan<192, 12> { using fwd = RadixList<3, 4, 4, 4>; using inv = RadixList<4, 4, 4, 3>; };
+template <> struct Plan<192, 24> { using fwd = RadixList<3, 8, 8>; using inv = RadixList<8, 8, 3>; };
+template <> struct Plan<768, 12> { using fwd = RadixList<3, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 3>; };
+template <> struct Plan<768, 24> { using fwd = RadixList<3, 8, 8, 4>; using inv = RadixList<4, 8, 8, 3>; };
 
 // Twiddle-table entries of a plan direction: NS (R - 1) per pass with NS > 1 (each
 // entry is a (hi, lo) pair of cx<T>).
@@ -311,24 +316,28 @@ struct TwSize {
 };
 
 // Copy NCX cx<T> values (a whole twiddle table) from global memory to LDS with the
-// NT threads of a block, in 16-byte pieces, all loads issued before any store (named
-// registers, not an array, so that nothing lands in scratch memory).
+// NT threads of a block, in 16-byte pieces: rounds of up to four pieces per thread,
+// all loads of a round issued before its stores (named registers, not an array, so
+// that nothing lands in scratch memory).
+template <int NT, int NCH, int B>
+__device__ __forceinline__ void stage_round(const uint4* __restrict__ s, uint4* __restrict__ d, int tid) {
+  uint4 t0 = {}, t1 = {}, t2 = {}, t3 = {};
+  if (B + tid < NCH) t0 = s[B + tid];
+  if (NCH > B + NT && B + tid + NT < NCH) t1 = s[B + tid + NT];
+  if (NCH > B + 2 * NT && B + tid + 2 * NT < NCH) t2 = s[B + tid + 2 * NT];
+  if (NCH > B + 3 * NT && B + tid + 3 * NT < NCH) t3 = s[B + tid + 3 * NT];
+  if (B + tid < NCH) d[B + tid] = t0;
+  if (NCH > B + NT && B + tid + NT < NCH) d[B + tid + NT] = t1;
+  if (NCH > B + 2 * NT && B + tid + 2 * NT < NCH) d[B + tid + 2 * NT] = t2;
+  if (NCH > B + 3 * NT && B + tid + 3 * NT < NCH) d[B + tid + 3 * NT] = t3;
+  if constexpr (NCH > B + 4 * NT) stage_round<NT, NCH, B + 4 * NT>(s, d, tid);
+}
+
 template <typename T, int NT, int NCX>
 __device__ __forceinline__ void stage_tw(cx<T>* __restrict__ dst, const void* __restrict__ src, int tid) {
   constexpr int NCH = NCX * (int)sizeof(cx<T>) / 16;
   static_assert(NCX * sizeof(cx<T>) % 16 == 0, "tables are whole 16-byte pieces");
-  static_assert(NCH <= 4 * NT, "at most four pieces per thread");
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(dst);
-  uint4 t0 = {}, t1 = {}, t2 = {}, t3 = {};
-  if (tid < NCH) t0 = s[tid];
-  if (NCH > NT && tid + NT < NCH) t1 = s[tid + NT];
-  if (NCH > 2 * NT && tid + 2 * NT < NCH) t2 = s[tid + 2 * NT];
-  if (NCH > 3 * NT && tid + 3 * NT < NCH) t3 = s[tid + 3 * NT];
-  if (tid < NCH) d[tid] = t0;
-  if (NCH > NT && tid + NT < NCH) d[tid + NT] = t1;
-  if (NCH > 2 * NT && tid + 2 * NT < NCH) d[tid + 2 * NT] = t2;
-  if (NCH > 3 * NT && tid + 3 * NT < NCH) d[tid + 3 * NT] = t3;
+  stage_round<NT, NCH, 0>(reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), tid);
 }
 
 template <typename T, int N, int E, int SIGN, int NS, int NC, int NBUF, int SYNC, int R, int... Rest>

@@ -67,12 +67,12 @@ struct PassArgs {
 
 // Register plans of the FFT line kernels: E elements per thread of a line of
 // length N (the radix sequence follows from N and E, see Plan<N, E>).  E = 8 for
-// powers of two and 12 for 384 are the defaults; the others are autotuning
-// alternatives (E = 4: twice the threads, E = 16 / 24: more registers per thread;
-// 384 with E = 24 needs more LDS than a CU has in FP64, so it is FP32 only).
+// powers of two and 12 for 3 * 2^k (192, 384, 768) are the defaults; the others are
+// autotuning alternatives (E = 4: twice the threads, E = 16 / 24: more registers per
+// thread; E = 24 needs more LDS than a CU has in FP64, so it is FP32 only).
 // esize: bytes of one real (4 or 8).
 constexpr bool plan_ok(int n, int e, int esize) {
-  return (n == 384) ? (e == 12 || (e == 24 && esize == 4))
+  return (n == 192 || n == 384 || n == 768) ? (e == 12 || (e == 24 && esize == 4))
                     : ((n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512) &&
                        (e == 4 || e == 8 || (e == 16 && n >= 64)));
 }

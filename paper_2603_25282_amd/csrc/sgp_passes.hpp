@@ -31,7 +31,7 @@ namespace sgp {
 // interleaved, one 8- or 16-byte LDS access each).
 template <int N> struct PadLine {
   static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 13 : N == 64 ? 5 : N == 384 ? 2
-                             : N == 32 ? 9 : N == 16 ? 1 : 1;
+                             : N == 768 ? 2 : N == 192 ? 15 : N == 32 ? 9 : N == 16 ? 1 : 1;
   static constexpr int size = N + N / 8 + extra;
 };
 
@@ -420,12 +420,14 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <typename T, int KIND, int E>
 __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
   constexpr int ES = (int)sizeof(T);
-  constexpr int BUF = cmax(cmax(cmax(batched_lds<64, E, KIND, ES>(), batched_lds<128, E, KIND, ES>()),
-                                cmax(batched_lds<256, E, KIND, ES>(), batched_lds<384, E, KIND, ES>())),
-                           batched_lds<512, E, KIND, ES>());
-  constexpr int TWM = cmax(cmax(cmax(batched_tw<64, E, KIND, ES>(), batched_tw<128, E, KIND, ES>()),
-                                cmax(batched_tw<256, E, KIND, ES>(), batched_tw<384, E, KIND, ES>())),
-                           batched_tw<512, E, KIND, ES>());
+  constexpr int BUF = cmax(cmax(cmax(cmax(batched_lds<64, E, KIND, ES>(), batched_lds<128, E, KIND, ES>()),
+                                     cmax(batched_lds<256, E, KIND, ES>(), batched_lds<384, E, KIND, ES>())),
+                                cmax(batched_lds<512, E, KIND, ES>(), batched_lds<192, E, KIND, ES>())),
+                           batched_lds<768, E, KIND, ES>());
+  constexpr int TWM = cmax(cmax(cmax(cmax(batched_tw<64, E, KIND, ES>(), batched_tw<128, E, KIND, ES>()),
+                                     cmax(batched_tw<256, E, KIND, ES>(), batched_tw<384, E, KIND, ES>())),
+                                cmax(batched_tw<512, E, KIND, ES>(), batched_tw<192, E, KIND, ES>())),
+                           batched_tw<768, E, KIND, ES>());
   constexpr int TWB = (TWM * (int)sizeof(cx<T>) + 15) / 16;
   __shared__ cx<T> lx[BUF > 0 ? BUF : 1];
   __shared__ uint4 ltwr[TWB > 0 ? TWB : 1];
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
       pass_body<T, NN, E, lines_per_block(NN, E), KIND>(psi, a, it.y, lx, ltw, gred);                   \
     break;
   switch (a.n_line) {
-    SGP_BCASE(64) SGP_BCASE(128) SGP_BCASE(256) SGP_BCASE(384) SGP_BCASE(512)
+    SGP_BCASE(64) SGP_BCASE(128) SGP_BCASE(192) SGP_BCASE(256) SGP_BCASE(384) SGP_BCASE(512) SGP_BCASE(768)
     default: break;
   }
 #undef SGP_BCASE
@@ -741,7 +743,7 @@ static hipError_t obs_kind(int kind, const cx<T>* psi, const PassArgs& a, double
 // line length with that E).  Each (T, E) pair is compiled in its own translation
 // unit.
 #define SGP_FOR_PLAN_N(E, X)                                     \
-  X(16, E) X(32, E) X(64, E) X(128, E) X(256, E) X(384, E) X(512, E)
+  X(16, E) X(32, E) X(64, E) X(128, E) X(192, E) X(256, E) X(384, E) X(512, E) X(768, E)
 
 template <typename T, int E>
 hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st) {

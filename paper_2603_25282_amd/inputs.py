@@ -110,6 +110,16 @@ def initial_state(cfg: Config):
         phi = np.exp(-r2 / 8.0) / (32.0 * np.sqrt(np.pi))
         psi = np.stack([phi, phi, 6.0 * np.sqrt(7.0) * phi, phi, phi]).astype(np.complex128)
         return psi
+    elif cfg.init in ("soc_i", "soc_ii"):
+        # Example "SOC effects" initial data, phi = exp(-|x|^2/2) / (16 sqrt(pi)) (2D):
+        # case i: psi_{+-2} = psi_{+-1} = phi, psi_0 = 6 sqrt7 phi;
+        # case ii: psi_{+-2} = phi (x + i y), psi_{+-1} = phi, psi_0 = 6 sqrt7 phi (x + i y);
+        # both of unit mass (the integral of r^2 exp(-r^2) is that of exp(-r^2), pi).
+        X, Y = co[:2]
+        phi = np.exp(-(X * X + Y * Y) / 2.0) / (16.0 * np.sqrt(np.pi))
+        w = np.ones_like(X, dtype=np.complex128) if cfg.init == "soc_i" else (X + 1j * Y)
+        psi = np.stack([phi * w, phi, 6.0 * np.sqrt(7.0) * phi * w, phi, phi * w]).astype(np.complex128)
+        return psi
     else:
         raise ValueError(cfg.init)
     return normalise(psi.astype(np.complex128), shape, L)
@@ -139,6 +149,15 @@ EX3 = Config("paper-ex3-case1", (512, 512), 16.0, (120.0, 1.0, 1.0, 0.2, 0.0, 1.
 # Example "Accuracy" (3D case): [-8, 8]^3, t = 0.3.
 ACC3D = Config("paper-acc-3d", (64, 64, 64), 8.0, (10.0, -1.0, 1.0, 0.2, 0.1, 1.0, 1.0, 1.0),
                order=2, tau=1.0 / 40.0, steps=12, seed=0, init="ini1")
+
+# Example "SOC effects" (2D): c = (243, 12.1, -13), Omega = 0.2, [-24, 24]^2 at
+# h = 1/16 (768^2), TS2, tau = 1e-3 to t = 1; gamma varies (case i: 0, 0.7, 2; case
+# ii: 0, 0.3, 1.2).  The example states no trap: the harmonic trap with
+# gx = gy = 1 is taken.
+SOC_I = Config("paper-soc-case1", (768, 768), 24.0, (243.0, 12.1, -13.0, 0.2, 0.7, 1.0, 1.0, 1.0),
+               order=2, tau=1e-3, steps=1000, seed=0, init="soc_i")
+SOC_II = Config("paper-soc-case2", (768, 768), 24.0, (243.0, 12.1, -13.0, 0.2, 0.3, 1.0, 1.0, 1.0),
+                order=2, tau=1e-3, steps=1000, seed=0, init="soc_ii")
 
 CONFIGS = {c.name: c for c in (C1, C2, C3, C5, ACC2D, ACC3D)}
 

@@ -80,9 +80,9 @@ def test_workspace_size_scales_with_grid_and_dtype():
 def test_plan_widths_and_plan_setters_without_device():
     L = sgp.lib()
     for n, want in ((16, [8, 4]), (32, [8, 4]), (64, [8, 4, 16]), (128, [8, 4, 16]), (256, [8, 4, 16]),
-                    (512, [8, 4, 16]), (384, [12, 24])):
+                    (512, [8, 4, 16]), (192, [12, 24]), (384, [12, 24]), (768, [12, 24])):
         assert sgp.plan_widths(n) == want
-        assert sgp.plan_widths(n, "complex128") == [e for e in want if not (n == 384 and e == 24)]
+        assert sgp.plan_widths(n, "complex128") == [e for e in want if e != 24]
     out = (ctypes.c_int * 1)()
     assert L.sgp_plan_widths(512, 0, out, 1) == 3 and out[0] == 8  # count even when truncated
     assert L.sgp_plan_widths(48, 0, out, 1) == -1

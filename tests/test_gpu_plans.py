@@ -77,6 +77,21 @@ def test_every_plan_512_and_384(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_every_plan_192_and_768(dtype):
+    # the other 3 * 2^k lengths (radix 3 with radix 4, or radix 8), x = 768 and
+    # y = 192 in one rectangular grid, every plan pair
+    cfg = I.with_(I.C2, shape=(192, 768), L=24.0, name="rect-192-768")
+    psi0 = I.initial_state(cfg)
+    ref = oracle.evolve(psi0, cfg.L, cfg.params, 4, 1e-3, 3)
+    for widths in plans_2d(768, 192, dtype):
+        print(f"case plans 192x768 {dtype} widths={widths}", flush=True)
+        got, _, _ = run_plan(cfg, dtype, widths, steps=3)
+        err = rel_l2(got, ref)
+        print("  rel l2", err)
+        assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
 def test_plans_3d(dtype):
     base = I.with_(I.C3, shape=(16, 32, 64), name="c3-plans")
     p = list(base.params)
