@@ -141,10 +141,9 @@ C5 = Config("2d-256-ts4-adjoint", (256, 256), 12.0, (300.0, -3.0, 6.0, 0.8, 1.0,
 ACC2D = Config("paper-acc-2d", (192, 192), 12.0, (100.0, -1.0, 1.0, 0.2, 0.3, 1.0, 1.0, 1.0),
                order=2, tau=1.0 / 80.0, steps=40, seed=0, init="ini1")
 # Example "dynamical laws" (2D), case i: c = (120, 1, 1), Omega = 0.2, isotropic trap,
-# no SOC, tau = 1e-3.  The paper's domain is [-24, 24]^2 at h = 1/16 (768^2); the
-# data decays like exp(-r^2/4) in density, so [-16, 16]^2 at the same h (512^2)
-# holds it to 1e-28.  Cases ii (gamma = 0.9) and iii (gx = 1.3) via with_().
-EX3 = Config("paper-ex3-case1", (512, 512), 16.0, (120.0, 1.0, 1.0, 0.2, 0.0, 1.0, 1.0, 1.0),
+# no SOC, tau = 1e-3, on the paper's domain [-24, 24]^2 at h = 1/16 (768^2).  Cases
+# ii (gamma = 0.9) and iii (gx = 1.3) via with_().
+EX3 = Config("paper-ex3-case1", (768, 768), 24.0, (120.0, 1.0, 1.0, 0.2, 0.0, 1.0, 1.0, 1.0),
              order=4, tau=1e-3, steps=12000, seed=0, init="ex3")
 # Example "Accuracy" (3D case): [-8, 8]^3, t = 0.3.
 ACC3D = Config("paper-acc-3d", (64, 64, 64), 8.0, (10.0, -1.0, 1.0, 0.2, 0.1, 1.0, 1.0, 1.0),

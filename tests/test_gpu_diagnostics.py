@@ -68,7 +68,7 @@ def test_example_dynamical_laws_case_i():
     # delta_x = delta_y = delta_r / 2); energy conserved up to the time discretisation.
     cfg = I.EX3
     T = 4.0
-    print(f"case Example dynamical laws i, 512^2 FP64, T={T}", flush=True)
+    print(f"case Example dynamical laws i, 768^2 FP64, T={T}", flush=True)
     out = run_ex3(cfg, T, 0.5)
     d0 = out[0]
     E0, lz0 = d0["energy"], d0["lz"]
