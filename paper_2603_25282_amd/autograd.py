@@ -89,6 +89,50 @@ def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0, pla
                          float(t0), plan)
 
 
+class _ToLab(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi, Omega, shape, L, t):
+        dtype = "complex64" if phi.dtype == torch.complex64 else "complex128"
+        s = Solver(shape, L, (0.0, 0.0, 0.0, float(Omega), 0.0, 1.0, 1.0, 1.0), dtype=dtype)
+        lab = phi.detach().clone().contiguous()
+        s.rotation_map(lab, t, -1)
+        ctx.s, ctx.t, ctx.hd = s, t, math.prod(2.0 * L / n for n in shape)
+        ctx.save_for_backward(lab)
+        return lab
+
+    @staticmethod
+    def backward(ctx, grad):
+        s, t = ctx.s, ctx.t
+        (lab,) = ctx.saved_tensors
+        g = grad.detach().to(lab.dtype).contiguous()
+        gin = g.clone()
+        s.rotation_map(gin, t, +1)  # the map is unitary (shears and phases): adjoint = inverse
+        dOm = None
+        if ctx.needs_input_grad[1]:
+            # the map rotates by the angle Omega t: d lab / d Omega = -i t J_z lab with
+            # J_z = L_z + F_z, so dJ/dOmega = -t Im<g, J_z lab>; Im<g, J_z lab> = Re<i g, J_z lab>
+            # by polarization from <u, J_z u> = (<Lz> + M)(u) / h^d (the observables)
+            u = 1j * g
+            op = s.observables((u + lab).contiguous())
+            om = s.observables((u - lab).contiguous())
+            im = ((op[3] + op[2]) - (om[3] + om[2])) / (4.0 * ctx.hd)
+            dOm = torch.tensor(-t * im, dtype=torch.float64)
+        return gin, dOm, None, None, None
+
+
+def to_lab(phi, Omega, shape, L, t):
+    """The lab-frame state Psi(t) = M_t^{-1} Phi(t) of a rotating-frame state
+    (sgp_rotation_map, eqs. RSDA1/RSDA2), differentiable: with respect to phi by the
+    map's adjoint (its inverse: every shear and the component phase are unitary), and
+    with respect to Omega (a 0-d FP64 tensor) through the rotation angle Omega t, by
+    the generator J_z = L_z + F_z (exact to the spectral accuracy of the rotation).
+    Use the same Omega tensor as in evolve's params to differentiate a lab-frame loss
+    through both."""
+    if not isinstance(Omega, torch.Tensor):
+        Omega = torch.tensor(float(Omega), dtype=torch.float64)
+    return _ToLab.apply(phi, Omega, tuple(shape), float(L), float(t))
+
+
 class _EnsembleEvolve(torch.autograd.Function):
     """Differentiable batched ensemble evolution: inputs (ens, meta, params, *psis)."""
 

@@ -100,3 +100,80 @@ def test_lab_frame_3d_matches_oracle():
     err = rel_l2(Solver.from_device_layout(psi.cpu().numpy()), ref)
     print("3D lab frame rel l2", err)
     assert err <= 1e-11
+
+
+def test_to_lab_gradients():
+    # J = Re <g, to_lab(Phi)> for a fixed smooth Phi: dJ/dPhi is the forward map of g
+    # (the map is unitary), checked against the oracle's map; dJ/dOmega (through the
+    # rotation angle Omega t) against central differences of the GPU map
+    import torch
+    from paper_2603_25282_amd.autograd import to_lab
+    from tests.test_oracle_scheme import smooth_state
+    from paper_2603_25282_amd.sgp import Solver
+    shape, L, T, Om0 = (64, 64), 8.0, 0.37, 0.5
+    phi = smooth_state(shape, L, seed=2)
+    g = smooth_state(shape, L, seed=3)
+    dev = torch.device("cuda:0")
+    print("case to_lab gradients 64^2 FP64", flush=True)
+    P = torch.from_numpy(Solver.to_device_layout(phi)).to(dev).requires_grad_(True)
+    G = torch.from_numpy(Solver.to_device_layout(g)).to(dev)
+    Om = torch.tensor(Om0, dtype=torch.float64, requires_grad=True)
+    J = torch.sum((torch.conj(G) * to_lab(P, Om, shape, L, T)).real)
+    J.backward()
+    params = (0.0, 0.0, 0.0, Om0, 0.0, 1.0, 1.0, 1.0)
+    want = oracle.rotation_map(g, L, params, T, forward=True)
+    got = Solver.from_device_layout(P.grad.cpu().numpy())
+    err = rel_l2(got, want)
+
+    def jv(om):
+        lab = to_lab(P.detach(), om, shape, L, T)
+        return float(torch.sum((torch.conj(G) * lab).real))
+    eps = 1e-5
+    fd = (jv(Om0 + eps) - jv(Om0 - eps)) / (2 * eps)
+    print(f"  state grad vs oracle map {err:.3e}; dJ/dOmega {float(Om.grad):.12e} fd {fd:.12e}", flush=True)
+    assert err <= 1e-12
+    assert abs(float(Om.grad) - fd) <= 1e-7 * abs(fd)
+
+
+def test_lab_frame_overlap_loss_gradients():
+    # lab-frame overlap loss J = 1 - |<Psi_tgt, Psi_lab(T)>_h|^2 through evolve and
+    # to_lab with one Omega: the total dJ/dOmega and a directional state derivative
+    # against central differences of the whole GPU forward (FP64)
+    import torch
+    from paper_2603_25282_amd.autograd import evolve, to_lab
+    from tests.test_oracle_scheme import smooth_state
+    from paper_2603_25282_amd.sgp import Solver
+    cfg = I.with_(I.C5, shape=(64, 64), L=8.0)
+    shape, L, prm = cfg.shape, cfg.L, cfg.params
+    tau, n = 1e-3, 20
+    T = n * tau
+    psi0 = smooth_state(shape, L, seed=4)
+    tgt = smooth_state(shape, L, seed=5)
+    v = smooth_state(shape, L, seed=6)
+    dev = torch.device("cuda:0")
+    h2 = (2 * L / shape[0]) * (2 * L / shape[1])
+    TG = torch.from_numpy(Solver.to_device_layout(tgt)).to(dev)
+
+    def loss(p0, par):
+        out = evolve(p0, par, shape, L, prm[5:8], tau, n, order=4, K=7)
+        lab = to_lab(out, par[1], shape, L, T)
+        o = h2 * torch.sum(torch.conj(TG) * lab)
+        return 1.0 - torch.abs(o) ** 2
+
+    print("case lab-frame overlap loss 64^2 FP64", flush=True)
+    p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(dev).requires_grad_(True)
+    par = torch.tensor([prm[4], prm[3], prm[0], prm[1], prm[2]], dtype=torch.float64, requires_grad=True)
+    J = loss(p0, par)
+    J.backward()
+    eps = 1e-5
+    with torch.no_grad():
+        dp = torch.zeros(5, dtype=torch.float64)
+        dp[1] = eps
+        fd_om = (float(loss(p0.detach(), par.detach() + dp)) - float(loss(p0.detach(), par.detach() - dp))) / (2 * eps)
+        V = torch.from_numpy(Solver.to_device_layout(v)).to(dev)
+        fd_v = (float(loss(p0.detach() + eps * V, par.detach())) - float(loss(p0.detach() - eps * V, par.detach()))) / (
+            2 * eps)
+    ad_v = float(torch.sum((torch.conj(p0.grad) * V).real))
+    print(f"  dJ/dOmega {float(par.grad[1]):.10e} fd {fd_om:.10e}; d/dv {ad_v:.10e} fd {fd_v:.10e}", flush=True)
+    assert abs(float(par.grad[1]) - fd_om) <= 1e-6 * abs(fd_om)
+    assert abs(ad_v - fd_v) <= 1e-6 * abs(fd_v)
