@@ -122,8 +122,15 @@ int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
  * in 2D); out[7] = h^d sum x y rho (lab frame; Lemma 1: d<Lz>/dt =
  * (gx^2 - gy^2) out[7] when gamma = 0); out[8] = W = 2 h^d Im sum conj(psi)
  * (x d_x + y d_y) psi with spectral derivatives, which equals d(delta_x +
- * delta_y)/dt when gamma = 0 (Lemma 2).  Synchronous. */
-int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[9]);
+ * delta_y)/dt when gamma = 0 (Lemma 2); out[9] = dM/dt and out[10] = d<Lz>/dt by
+ * the laws of Sec. 2 (magnetization, and Lemma 1 with its spin-orbit term), from
+ * the sums h^d sum conj(psi_a) L_+- psi_b (L_+- = i d_y +- d_x, spectral) over the
+ * adjacent component pairs: dM/dt = -2 gamma Im[Q1 + Q2 + sqrt6/2 (Q3 - Q4)] and
+ * d<Lz>/dt = (gx^2 - gy^2) out[7] + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] with
+ * Q1 = <psi_2, L_- psi_1>, Q2 = <psi_-1, L_- psi_-2>, Q3 = <psi_1, L_- psi_0>,
+ * Q4 = <psi_-1, L_+ psi_0>, Q5 = <psi_1, L_+ psi_2>; all frame-invariant.
+ * Synchronous. */
+int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[11]);
 
 /* ---- Differentiation (discrete adjoint of sgp_step) -------------------------
  * Convention: for a real loss J of the state, a gradient is g = 2 dJ/d conj(psi),

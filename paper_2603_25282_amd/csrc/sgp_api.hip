@@ -588,7 +588,7 @@ long pass_nblocks(const sgp_ctx* c, int axis, int e) {
 }
 
 template <typename T>
-int observables_impl(sgp_ctx* c, const void* psi, double out[9]) {
+int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
   double* part = (double*)c->at(c->off_part);
   double tot[3][NOBS];
   for (int axis = 0; axis < c->g.dim; ++axis) {
@@ -631,6 +631,26 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[9]) {
   out[6] = hd * tot[0][9];
   out[7] = hd * tot[0][10];
   out[8] = hd * (tot[0][11] + tot[1][11]);
+  // spin-orbit laws (Sec. 2): with L_+- = i d_y +- d_x and the sums
+  // D_a(q) = sum conj(psi_a) d_a psi_b over the pairs q, Q = sum conj(psi_a) L psi_b
+  // = i D_y +- D_x; the pair (1, 2) follows from (2, 1) since d is anti-Hermitian
+  using cd = std::complex<double>;
+  auto dsum = [&](int axis, int q) {
+    const int base = axis == 0 ? 12 : 20;
+    return cd(tot[axis][base + 2 * q], tot[axis][base + 2 * q + 1]);
+  };
+  auto lsum = [&](int q, double sgn) { return cd(0.0, 1.0) * dsum(1, q) + sgn * dsum(0, q); };
+  const cd q1 = lsum(0, -1.0);  // conj(psi_2) L_- psi_1
+  const cd q2 = lsum(1, -1.0);  // conj(psi_-1) L_- psi_-2
+  const cd q3 = lsum(2, -1.0);  // conj(psi_1) L_- psi_0
+  const cd q4 = lsum(3, +1.0);  // conj(psi_-1) L_+ psi_0
+  const cd q5 = cd(0.0, 1.0) * (-std::conj(dsum(1, 0))) - std::conj(dsum(0, 0));  // conj(psi_1) L_+ psi_2
+  const double r6h = 1.22474487139158904909864203735294570;
+  const double g = c->p.gamma;
+  // out[9] = dM/dt = -2 gamma Im[Q1 + Q2 + sqrt6/2 (Q3 - Q4)]
+  out[9] = -2.0 * g * hd * (q1 + q2 + r6h * (q3 - q4)).imag();
+  // out[10] = d<Lz>/dt = (gx^2 - gy^2) int x y rho + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] (Lemma 1)
+  out[10] = (c->p.gx * c->p.gx - c->p.gy * c->p.gy) * out[7] + 2.0 * g * hd * (q2 - q5 + r6h * (q3 - q4)).imag();
   return SGP_OK;
 }
 
@@ -909,13 +929,13 @@ int sgp_rotation_map(sgp_ctx* c, void* psi, double t, int direction) {
 int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
-  double all[9];
+  double all[11];
   int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
   if (rc == SGP_OK) std::memcpy(out, all, 4 * sizeof(double));
   return rc;
 }
 
-int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[9]) {
+int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[11]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   return c->dtype == SGP_C64 ? observables_impl<float>(c, psi, out) : observables_impl<double>(c, psi, out);

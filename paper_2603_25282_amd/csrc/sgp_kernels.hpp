@@ -15,7 +15,7 @@ enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, 
 enum { NGRAD = 5 };  // adjoint parameter slots: gamma, Omega, c0, c1, c2
 enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2 };
 enum { CLOCK_ARG = 0, CLOCK_DEVICE = 1 };
-enum { NOBS = 12 };  // partial sums per block of the observables kernels
+enum { NOBS = 28 };  // partial sums per block of the observables kernels
 
 // One pass over lines of the state ([nz][ny][nx][5] complex).  X kinds use the
 // x-line fields, column kinds (C_*) the column fields; both read the tables.

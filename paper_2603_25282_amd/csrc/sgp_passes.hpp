@@ -601,6 +601,16 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
       acc[9] += z * z * rho;
       acc[10] += X * Y * rho;
       acc[11] += 2.0 * x * rot;
+      // conj(psi_a) d_x psi_b for the component pairs (a, b) = (2, 1), (-1, -2),
+      // (1, 0), (-1, 0) (indices 0..4 = l 2..-2) of the spin-orbit laws
+      acc[12] += pr[0] * dr[1] + pi[0] * di[1];
+      acc[13] += pr[0] * di[1] - pi[0] * dr[1];
+      acc[14] += pr[3] * dr[4] + pi[3] * di[4];
+      acc[15] += pr[3] * di[4] - pi[3] * dr[4];
+      acc[16] += pr[1] * dr[2] + pi[1] * di[2];
+      acc[17] += pr[1] * di[2] - pi[1] * dr[2];
+      acc[18] += pr[3] * dr[2] + pi[3] * di[2];
+      acc[19] += pr[3] * di[2] - pi[3] * dr[2];
     } else {
       acc[4] += 0.5 * grad2;
       if constexpr (KIND == OBS_Y) {
@@ -612,6 +622,15 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
           s += w[l] * ((pr[l] * di[l + 1] - pi[l] * dr[l + 1]) + (pr[l + 1] * di[l] - pi[l + 1] * dr[l]));
         acc[6] += -s;
         acc[11] += 2.0 * y * rot;
+        // conj(psi_a) d_y psi_b for the same pairs
+        acc[20] += pr[0] * dr[1] + pi[0] * di[1];
+        acc[21] += pr[0] * di[1] - pi[0] * dr[1];
+        acc[22] += pr[3] * dr[4] + pi[3] * di[4];
+        acc[23] += pr[3] * di[4] - pi[3] * dr[4];
+        acc[24] += pr[1] * dr[2] + pi[1] * di[2];
+        acc[25] += pr[1] * di[2] - pi[1] * dr[2];
+        acc[26] += pr[3] * dr[2] + pi[3] * di[2];
+        acc[27] += pr[3] * di[2] - pi[3] * dr[2];
       }
     }
   }

@@ -25,6 +25,24 @@ def reference(psi, L, theta):
     return (h2 * np.sum(Xr ** 2 * rho), h2 * np.sum(Yr ** 2 * rho), h2 * np.sum(Xr * Yr * rho), W)
 
 
+def soc_rates(psi, L, params, xy):
+    """dM/dt and d<Lz>/dt by the laws of Sec. 2 written out in numpy (L_+- = i d_y +- d_x,
+    spectral derivatives), for checking the device sums against their definition."""
+    ny, nx = psi.shape[1:]
+    h2 = (2 * L / nx) * (2 * L / ny)
+    g = [spectral_grad(psi[c], L) for c in range(5)]  # (d_x, d_y) per component; index 0..4 = l 2..-2
+    lp = lambda c: 1j * g[c][1] + g[c][0]
+    lm = lambda c: 1j * g[c][1] - g[c][0]
+    ip = lambda a, b: h2 * np.sum(np.conj(psi[a]) * b)
+    q1, q2, q3 = ip(0, lm(1)), ip(3, lm(4)), ip(1, lm(2))
+    q4, q5 = ip(3, lp(2)), ip(1, lp(0))
+    r6h = np.sqrt(6.0) / 2
+    gam, gx, gy = params[4], params[5], params[6]
+    dM = -2 * gam * np.imag(q1 + q2 + r6h * (q3 - q4))
+    dLz = (gx ** 2 - gy ** 2) * xy + 2 * gam * np.imag(q2 - q5 + r6h * (q3 - q4))
+    return dM, dLz
+
+
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
 def test_diagnostics_match_definitions(dtype):
     from paper_2603_25282_amd.sgp import Solver
@@ -36,8 +54,9 @@ def test_diagnostics_match_definitions(dtype):
     s.time = t
     d = s.diagnostics(to_gpu(s, psi))
     dx, dy, xy, W = reference(psi, L, params[3] * t)
-    got = np.array([d["delta_x"], d["delta_y"], d["xy_rho"], d["width_rate"]])
-    ref = np.array([dx, dy, xy, W])
+    dM, dLz = soc_rates(psi, L, params, xy)
+    got = np.array([d["delta_x"], d["delta_y"], d["xy_rho"], d["width_rate"], d["dM_dt"], d["dLz_dt"]])
+    ref = np.array([dx, dy, xy, W, dM, dLz])
     print("gpu", got, "ref", ref, flush=True)
     tol = 1e-12 if dtype == "complex128" else 3e-6
     assert np.all(np.abs(got - ref) <= tol * np.maximum(1.0, np.abs(ref)))
@@ -118,3 +137,28 @@ def test_example_dynamical_laws_cases_ii_iii():
     print(f"d<Lz>/dt by differences {dlz:.10e}, law {law:.10e}", flush=True)
     assert abs(law) > 1e-4
     assert abs(dlz - law) < 1e-3 * abs(law)
+
+
+def test_spin_orbit_laws_by_differences():
+    # gamma = 0.9 and an anisotropic trap (gx = 1.3) on the dynamical-laws example:
+    # the device's dM/dt (magnetization law, spin-orbit term) and d<Lz>/dt (Lemma 1
+    # with its spin-orbit term) against central differences of M(t) and <Lz>(t) of the
+    # same GPU trajectory (FP64, TS4, tau = 1e-3)
+    p = list(I.EX3.params)
+    p[4], p[5] = 0.9, 1.3
+    cfg = I.with_(I.EX3, params=tuple(p), name="ex3-soc-aniso")
+    # central differences at dt and dt/2, Richardson-extrapolated (error O(dt^4));
+    # the trajectory's own error is O(tau^4)
+    t0, dt = 0.5, 0.02
+    print("case spin-orbit laws by differences, 768^2 FP64", flush=True)
+    out = run_ex3(cfg, t0, t0, extra_times=(t0 - dt, t0 + dt, t0 - dt / 2, t0 + dt / 2))
+    m = lambda t: round(t / cfg.tau)
+    for key, rate in (("magnetization", "dM_dt"), ("lz", "dLz_dt")):
+        f1 = (out[m(t0 + dt)][key] - out[m(t0 - dt)][key]) / (2 * dt)
+        f2 = (out[m(t0 + dt / 2)][key] - out[m(t0 - dt / 2)][key]) / dt
+        fd = (4 * f2 - f1) / 3
+        law = out[m(t0)][rate]
+        print(f"  d{key}/dt by differences {f1:.10e} (dt), {f2:.10e} (dt/2), extrapolated {fd:.10e}; "
+              f"law {law:.10e}", flush=True)
+        assert abs(law) > 1e-3
+        assert abs(fd - law) <= 1e-5 * abs(law)
