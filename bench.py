@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--dtype", default="complex64", choices=["complex64", "complex128"])
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "ensemble"])
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "ensemble", "paper-eff"])
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=50)
@@ -59,6 +59,8 @@ def main():
 
     if a.workload == "ensemble":
         return bench_ensemble(a)
+    if a.workload == "paper-eff":
+        return bench_paper_efficiency(a)
     from paper_2603_25282_amd import inputs as I
     from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, Solver
 
@@ -309,6 +311,66 @@ def bench_ensemble(a):
         "config": {"workload": "ensemble-96", "grids": "32x128^2 + 48x256^2 + 16x384^2", "points": npts,
                    "L": insts[0].L, "scheme": "TS2", "tau": insts[0].tau, "plans": ens.plans(), "finite": finite},
         "bytes_model": {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9}, "fwd_adjoint": adj}), flush=True)
+
+
+# The paper's Table Eff1 (Example "Efficiency"): seconds to advance t = 0 -> 0.1
+# (tau = 1e-3, 100 steps) on a dual-socket Xeon Gold 6248R, FORTRAN, Algorithm 1.
+PAPER_EFF1_S = {(2, 2): [0.68, 2.99, 8.12, 17.77], (2, 4): [1.57, 7.02, 18.03, 40.71],
+                (3, 2): [75.22, 622.01, 2449.06, 6137.38], (3, 4): [172.46, 1643.12, 5671.32, 14688.66]}
+
+
+def bench_paper_efficiency(a):
+    """The paper's Example "Efficiency" workloads on the GPU: c = (10, 1, 1),
+    Omega = 0.2, gamma = 0.1, isotropic trap, initial data ini1, [-12, 12]^d, N^d with
+    N in {64, 128, 192, 256}, d = 2 and 3, TS2 and TS4, tau = 1e-3 from t = 0 to 0.1
+    (100 steps).  Each is timed (after one untimed run) three ways: Algorithm 1 as
+    the paper runs it (lab frame, rotation mapping around every linear substep) in
+    FP64 -- the like-for-like of Table Eff1 -- and the rotating-frame path in FP64 and
+    in FP32.  Seconds per 100 steps; the paper's seconds are context (other
+    hardware)."""
+    import torch
+    from paper_2603_25282_amd import inputs as I
+    from paper_2603_25282_amd.sgp import Solver
+    params = (10.0, 1.0, 1.0, 0.2, 0.1, 1.0, 1.0, 1.0)
+    rows = []
+    for d in (2, 3):
+        for order in (2, 4):
+            for k, n in enumerate((64, 128, 192, 256)):
+                cfg = I.Config("paper-eff", (n,) * d, 12.0, params, order=order, tau=1e-3, steps=100, seed=0,
+                               init="ini1")
+                psi0 = I.initial_state(cfg)
+                row = {"d": d, "scheme": f"TS{order}", "N": n, "paper_s": PAPER_EFF1_S[(d, order)][k]}
+                for label, dtype, frame in (("alg1_lab_f64", "complex128", "lab"), ("rotating_f64", "complex128",
+                                             "rotating"), ("rotating_f32", "complex64", "rotating")):
+                    s = Solver(cfg.shape, cfg.L, params, dtype=dtype)
+                    s.build_propagator(cfg.tau, order)
+                    s.set_frame(frame)
+                    psi = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).cuda().contiguous()
+                    times = []
+                    for _ in range(2):
+                        q = psi.clone()
+                        s.time = 0.0
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        s.step(q, cfg.steps)
+                        torch.cuda.synchronize()
+                        times.append(time.perf_counter() - t0)
+                    row[label + "_s"] = times[-1]
+                    del q, psi, s
+                row["speedup_alg1_f64"] = row["paper_s"] / row["alg1_lab_f64_s"]
+                row["speedup_rotating_f64"] = row["paper_s"] / row["rotating_f64_s"]
+                print(f"# paper-eff d={d} TS{order} N={n}: paper {row['paper_s']} s, Algorithm 1 FP64 "
+                      f"{row['alg1_lab_f64_s']:.4f} s, rotating FP64 {row['rotating_f64_s']:.4f} s, rotating FP32 "
+                      f"{row['rotating_f32_s']:.4f} s", file=sys.stderr, flush=True)
+                rows.append(row)
+    big = [r for r in rows if r["d"] == 3 and r["N"] == 256 and r["scheme"] == "TS4"][0]
+    print(json.dumps({
+        "metric": "seconds per 100 steps, the paper's Example Efficiency (Table Eff1 workloads)",
+        "value": big["alg1_lab_f64_s"], "unit": "s", "n_gpus": 1, "steps": 100, "warmup": 1,
+        "ms_per_step": big["alg1_lab_f64_s"] * 10, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (the paper's analytic initial data ini1)",
+        "config": {"workload": "paper-efficiency", "headline": "3D 256^3 TS4, Algorithm 1 (lab frame), FP64",
+                   "params": list(params), "L": 12.0, "tau": 1e-3, "rows": rows}}), flush=True)
 
 
 class UnfusedFP64:
