@@ -263,7 +263,7 @@ def bench_ensemble(a):
             for c in insts]
     ens.build_propagator(insts[0].tau, insts[0].order)
     if a.plan == "auto":
-        ens.autotune(psis, steps=10)
+        ens.autotune(psis, steps=40)
     npts = sum(c.points for c in insts)
     steps = min(a.steps, 500)
     ens.step(psis, a.warmup)

@@ -117,6 +117,27 @@ struct Dft<4, SIGN, T> {
   }
 };
 
+// Length 6 = 2 * 3 by the prime-factor (Good-Thomas) mapping, which needs no inner
+// twiddles: input n = (3 n1 + 2 n2) mod 6, output k = (3 k1 + 4 k2) mod 6, so that
+// exp(2 pi i n k / 6) = exp(2 pi i n1 k1 / 2) exp(2 pi i n2 k2 / 3).
+template <int SIGN, typename T>
+struct Dft<6, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    // length-2 transforms over n1 for n2 = 0, 1, 2 (inputs (0, 3), (2, 5), (4, 1))
+    cx<T> y0[3] = {x[0] + x[3], x[2] + x[5], x[4] + x[1]};  // k1 = 0
+    cx<T> y1[3] = {x[0] - x[3], x[2] - x[5], x[4] - x[1]};  // k1 = 1
+    // length-3 transforms over n2; k2 = 0, 1, 2 land at (3 k1 + 4 k2) mod 6
+    Dft<3, SIGN, T>::run(y0);
+    Dft<3, SIGN, T>::run(y1);
+    x[0] = y0[0];
+    x[4] = y0[1];
+    x[2] = y0[2];
+    x[3] = y1[0];
+    x[1] = y1[1];
+    x[5] = y1[2];
+  }
+};
+
 template <int SIGN, typename T>
 struct Dft<8, SIGN, T> {
   __device__ __forceinline__ static void run(cx<T>* x) {
@@ -288,8 +309,8 @@ template <> struct Plan<128, 16> { using fwd = RadixList<2, 8, 8>; using inv = R
 template <> struct Plan<256, 16> { using fwd = RadixList<4, 8, 8>; using inv = RadixList<8, 8, 4>; };
 template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = RadixList<8, 8, 8>; };
 // 384 = 3 * 2^7: E = 12 (default) and E = 24
-template <> struct Plan<384, 12> { using fwd = RadixList<3, 4, 4, 4, 2>; using inv = RadixList<2, 4, 4, 4, 3>; };
-template <> struct Plan<384, 24> { using fwd = RadixList<3, 8, 8, 2>; using inv = RadixList<2, 8, 8, 3>; };
+template <> struct Plan<384, 12> { using fwd = RadixList<6, 4, 4, 4>; using inv = RadixList<4, 4, 4, 6>; };
+template <> struct Plan<384, 24> { using fwd = RadixList<6, 8, 8>; using inv = RadixList<8, 8, 6>; };
 // 192 = 3 * 2^6 and 768 = 3 * 2^8: E = 12 (default) and E = 24
 template <> struct Plan<192, 12> { using fwd = RadixList<3, 4, 4, 4>; using inv = RadixList<4, 4, 4, 3>; };
 template <> struct Plan<192, 24> { using fwd = RadixList<3, 8, 8>; using inv = RadixList<8, 8, 3>; };
