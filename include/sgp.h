@@ -265,14 +265,16 @@ int sgp_ensemble_set_option(sgp_ensemble* ens, int option, long value);
 /* Register plans of an ensemble (see sgp_set_plan): the width used along `axis`
  * (0 = x-lines, 1 = y-lines) by every instance of size n x n.  Batched kernels
  * run the 320-thread geometry, so the widths available are those of
- * sgp_plan_widths(n, dtype) with n/E <= 64 (all but E = 4 at n = 512).  Each pass
- * type of a step is one batched launch per plan width in use.
+ * sgp_plan_widths(n, dtype) with n/E <= 64 (all but E = 4 at n = 512).  The
+ * instances sharing an (x, y) width pair form a partition; each partition runs its
+ * passes (one batched launch per pass) on its own stream.
  * sgp_ensemble_set_plan: elems = 0 restores the default; SGP_ERR_ARG if the width
  *   is not available or no instance has size n.  Drops the captured step graph.
  * sgp_ensemble_get_plan: the width of the first instance of size n.
- * sgp_ensemble_autotune: for each instance size and axis in turn (the others at
- *   their current best), times `steps` ensemble steps per candidate width (after
- *   one untimed call of `steps` steps) and keeps the fastest; psi_devs are
+ * sgp_ensemble_autotune: for each instance size in turn (the others at their
+ *   current best), times `steps` ensemble steps for every (x, y) width pair (after
+ *   one untimed call of `steps` steps) and keeps the fastest, sweeping over the
+ *   sizes until a sweep improves nothing (at most three sweeps); psi_devs are
  *   advanced by every step (pass scratch copies); the ensemble time is restored;
  *   ms_per_step (if not NULL) receives the fastest time per step. */
 int sgp_ensemble_set_plan(sgp_ensemble* ens, int n, int axis, int elems);

@@ -1091,7 +1091,7 @@ struct sgp_ensemble {
   // lists; each partition's launches run on their own stream (one batched launch
   // per pass and partition)
   size_t off_items[2] = {0, 0}, off_args = 0;
-  struct Part { int ex, ey; long off[2], n[2]; };
+  struct Part { int ex, ey, nmax; long off[2], n[2]; };
   std::vector<Part> parts;
   char* ws = nullptr;
   int nslots = 0;  // PassArgs slots (per instance): see ens_slots()
@@ -1212,7 +1212,12 @@ hipError_t ens_build_items(sgp_ensemble* e) {
   }
   std::sort(pairs.begin(), pairs.end());
   e->parts.clear();
-  for (const auto& wp : pairs) e->parts.push_back(sgp_ensemble::Part{wp.first, wp.second, {0, 0}, {0, 0}});
+  for (const auto& wp : pairs) {
+    sgp_ensemble::Part P{wp.first, wp.second, 0, {0, 0}, {0, 0}};
+    for (auto* c : e->ctx)
+      if (c->plan_e[0] == P.ex && c->plan_e[1] == P.ey) P.nmax = std::max(P.nmax, c->g.n[0]);
+    e->parts.push_back(P);
+  }
   for (int ax = 0; ax < 2; ++ax) {
     std::vector<int2> items;
     for (auto& P : e->parts) {
@@ -1240,7 +1245,7 @@ hipError_t ens_launch_part(sgp_ensemble* e, const sgp_ensemble::Part& P, hipStre
   const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
   const int ax = xl ? 0 : 1;
   const int2* items = (const int2*)(e->ws + e->off_items[ax]);
-  return launch_pass_batched<T>(kind, ax == 0 ? P.ex : P.ey, items + P.off[ax], args, P.n[ax], st);
+  return launch_pass_batched<T>(kind, ax == 0 ? P.ex : P.ey, items + P.off[ax], args, P.n[ax], P.nmax, st);
 }
 
 // Run fn(partition, stream) for every partition, each on its own stream, between one
@@ -1435,7 +1440,8 @@ int ens_adjoint_run(sgp_ensemble* e, void* const* states, long nsteps, char* sto
     for (size_t L = 0; L < kinds.size() && rr == hipSuccess; ++L) {
       const int ax = (kinds[L] == C_PROP || kinds[L] == C_ADJ) ? 1 : 0;
       const int2* items = (const int2*)(e->ws + e->off_items[ax]);
-      rr = launch_pass_batched<T>(kinds[L], ax == 0 ? P.ex : P.ey, items + P.off[ax], args + L * e->n, P.n[ax], sst);
+      rr = launch_pass_batched<T>(kinds[L], ax == 0 ? P.ex : P.ey, items + P.off[ax], args + L * e->n, P.n[ax],
+                                  P.nmax, sst);
     }
     return rr;
   });
@@ -1630,22 +1636,34 @@ int sgp_ensemble_autotune(sgp_ensemble* e, void* const* psi_devs, int steps, dou
   double best = 0.0;
   int rc = time_steps(&best);
   const int esize = e->dtype == SGP_C64 ? 4 : 8;
-  for (size_t k = 0; k < sizes.size() && rc == SGP_OK; ++k)
-    for (int ax = 0; ax < 2 && rc == SGP_OK; ++ax) {
+  // per instance size, every (x, y) plan pair with the other sizes at their current
+  // best (the partitions of different sizes run concurrently, so the choices
+  // interact); sweeps over the sizes repeat until one improves nothing (at most 3)
+  for (int sweep = 0; sweep < 3 && rc == SGP_OK; ++sweep) {
+    bool improved = false;
+    for (size_t k = 0; k < sizes.size() && rc == SGP_OK; ++k) {
       const int n = sizes[k];
-      int start = 0;
-      sgp_ensemble_get_plan(e, n, ax, &start);
-      int best_w = start;
-      for (int w : kPlanElems) {
-        if (w == start || !batched_plan_ok(n, w, esize)) continue;
-        double ms = 0.0;
-        rc = sgp_ensemble_set_plan(e, n, ax, w);
-        if (rc == SGP_OK) rc = time_steps(&ms);
+      int sx = 0, sy = 0;
+      sgp_ensemble_get_plan(e, n, 0, &sx);
+      sgp_ensemble_get_plan(e, n, 1, &sy);
+      int bx = sx, by = sy;
+      for (int wx : kPlanElems) {
+        for (int wy : kPlanElems) {
+          if ((wx == sx && wy == sy) || !batched_plan_ok(n, wx, esize) || !batched_plan_ok(n, wy, esize)) continue;
+          double ms = 0.0;
+          rc = sgp_ensemble_set_plan(e, n, 0, wx);
+          if (rc == SGP_OK) rc = sgp_ensemble_set_plan(e, n, 1, wy);
+          if (rc == SGP_OK) rc = time_steps(&ms);
+          if (rc != SGP_OK) break;
+          if (ms < best) { best = ms; bx = wx; by = wy; improved = true; }
+        }
         if (rc != SGP_OK) break;
-        if (ms < best) { best = ms; best_w = w; }
       }
-      if (rc == SGP_OK) rc = sgp_ensemble_set_plan(e, n, ax, best_w);
+      if (rc == SGP_OK) rc = sgp_ensemble_set_plan(e, n, 0, bx);
+      if (rc == SGP_OK) rc = sgp_ensemble_set_plan(e, n, 1, by);
     }
+    if (!improved) break;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   e->t = t_save;

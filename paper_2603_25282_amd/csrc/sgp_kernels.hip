@@ -13,7 +13,7 @@ SGP_EXTERN(float, 4) SGP_EXTERN(float, 8) SGP_EXTERN(float, 12) SGP_EXTERN(float
 SGP_EXTERN(double, 4) SGP_EXTERN(double, 8) SGP_EXTERN(double, 12) SGP_EXTERN(double, 16) SGP_EXTERN(double, 24)
 #undef SGP_EXTERN
 #define SGP_EXTERN_B(TT, EE) \
-  extern template hipError_t launch_batched_e<TT, EE>(int, const int2*, const PassArgs*, long, hipStream_t);
+  extern template hipError_t launch_batched_e<TT, EE>(int, const int2*, const PassArgs*, long, int, hipStream_t);
 SGP_EXTERN_B(float, 4) SGP_EXTERN_B(float, 8) SGP_EXTERN_B(float, 12) SGP_EXTERN_B(float, 16) SGP_EXTERN_B(float, 24)
 SGP_EXTERN_B(double, 4) SGP_EXTERN_B(double, 8) SGP_EXTERN_B(double, 12) SGP_EXTERN_B(double, 16)
 #undef SGP_EXTERN_B
@@ -58,24 +58,25 @@ hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, 
 }
 
 template <typename T>
-hipError_t launch_pass_batched(int kind, int e, const void* items, const void* args, long nitems, hipStream_t st) {
+hipError_t launch_pass_batched(int kind, int e, const void* items, const void* args, long nitems, int nmax,
+                               hipStream_t st) {
   const int2* it = (const int2*)items;
   const PassArgs* ar = (const PassArgs*)args;
   if (nitems <= 0) return hipSuccess;
   switch (e) {
-    case 4: return launch_batched_e<T, 4>(kind, it, ar, nitems, st);
-    case 8: return launch_batched_e<T, 8>(kind, it, ar, nitems, st);
-    case 12: return launch_batched_e<T, 12>(kind, it, ar, nitems, st);
-    case 16: return launch_batched_e<T, 16>(kind, it, ar, nitems, st);
+    case 4: return launch_batched_e<T, 4>(kind, it, ar, nitems, nmax, st);
+    case 8: return launch_batched_e<T, 8>(kind, it, ar, nitems, nmax, st);
+    case 12: return launch_batched_e<T, 12>(kind, it, ar, nitems, nmax, st);
+    case 16: return launch_batched_e<T, 16>(kind, it, ar, nitems, nmax, st);
     case 24:
-      if constexpr (sizeof(T) == 4) return launch_batched_e<T, 24>(kind, it, ar, nitems, st);
+      if constexpr (sizeof(T) == 4) return launch_batched_e<T, 24>(kind, it, ar, nitems, nmax, st);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_pass_batched<float>(int, int, const void*, const void*, long, hipStream_t);
-template hipError_t launch_pass_batched<double>(int, int, const void*, const void*, long, hipStream_t);
+template hipError_t launch_pass_batched<float>(int, int, const void*, const void*, long, int, hipStream_t);
+template hipError_t launch_pass_batched<double>(int, int, const void*, const void*, long, int, hipStream_t);
 template hipError_t launch_pass<float>(int, void*, const PassArgs&, int, int, hipStream_t);
 template hipError_t launch_pass<double>(int, void*, const PassArgs&, int, int, hipStream_t);
 template hipError_t launch_obs<float>(int, const void*, const PassArgs&, int, int, double*, hipStream_t);

@@ -99,8 +99,10 @@ hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, 
 constexpr bool batched_plan_ok(int n, int e, int esize) { return n >= 64 && plan_ok(n, e, esize) && n / e <= 64; }
 // batched passes of one plan width e: items = int2 (instance, tile) of instances
 // using width e along the pass's axis, args = PassArgs per instance
+// nmax: the longest line among the instances of the launch
 template <typename T>
-hipError_t launch_pass_batched(int kind, int e, const void* items, const void* args, long nitems, hipStream_t st);
+hipError_t launch_pass_batched(int kind, int e, const void* items, const void* args, long nitems, int nmax,
+                               hipStream_t st);
 
 // per-plan-width launchers, each (T, E) compiled in its own translation unit
 template <typename T, int E>

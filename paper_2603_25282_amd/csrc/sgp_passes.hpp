@@ -417,17 +417,20 @@ constexpr int batched_tw() {
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <typename T, int KIND, int E>
+// NMAX: the longest line the kernel serves (512, or 768 for the E = 12 / 24 plans);
+// its static LDS is sized for lines up to NMAX only, so instances of the common
+// sizes keep the occupancy they have without 768-point lines in the ensemble.
+template <typename T, int KIND, int E, int NMAX>
 __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ items, const PassArgs* __restrict__ args) {
   constexpr int ES = (int)sizeof(T);
   constexpr int BUF = cmax(cmax(cmax(cmax(batched_lds<64, E, KIND, ES>(), batched_lds<128, E, KIND, ES>()),
                                      cmax(batched_lds<256, E, KIND, ES>(), batched_lds<384, E, KIND, ES>())),
                                 cmax(batched_lds<512, E, KIND, ES>(), batched_lds<192, E, KIND, ES>())),
-                           batched_lds<768, E, KIND, ES>());
+                           NMAX >= 768 ? batched_lds<768, E, KIND, ES>() : 0);
   constexpr int TWM = cmax(cmax(cmax(cmax(batched_tw<64, E, KIND, ES>(), batched_tw<128, E, KIND, ES>()),
                                      cmax(batched_tw<256, E, KIND, ES>(), batched_tw<384, E, KIND, ES>())),
                                 cmax(batched_tw<512, E, KIND, ES>(), batched_tw<192, E, KIND, ES>())),
-                           batched_tw<768, E, KIND, ES>());
+                           NMAX >= 768 ? batched_tw<768, E, KIND, ES>() : 0);
   constexpr int TWB = (TWM * (int)sizeof(cx<T>) + 15) / 16;
   __shared__ cx<T> lx[BUF > 0 ? BUF : 1];
   __shared__ uint4 ltwr[TWB > 0 ? TWB : 1];
@@ -438,7 +441,7 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.state);
 #define SGP_BCASE(NN)                                                                                  \
   case NN:                                                                                             \
-    if constexpr (batched_plan_ok(NN, E, ES))                                                          \
+    if constexpr (NN <= NMAX && batched_plan_ok(NN, E, ES))                                            \
       pass_body<T, NN, E, lines_per_block(NN, E), KIND>(psi, a, it.y, lx, ltw, gred);                   \
     break;
   switch (a.n_line) {
@@ -789,21 +792,31 @@ hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, dou
 }
 
 // Batched passes of one plan width (compiled with that width's unit).
-template <typename T, int E>
-hipError_t launch_batched_e(int kind, const int2* it, const PassArgs* ar, long nitems, hipStream_t st) {
+template <typename T, int E, int NMAX>
+static hipError_t launch_batched_nmax(int kind, const int2* it, const PassArgs* ar, long nitems, hipStream_t st) {
   dim3 g((unsigned)nitems), b(320);
   switch (kind) {
-    case X_FIRST: hipLaunchKernelGGL((k_pass_batched<T, X_FIRST, E>), g, b, 0, st, it, ar); break;
-    case X_MID: hipLaunchKernelGGL((k_pass_batched<T, X_MID, E>), g, b, 0, st, it, ar); break;
-    case X_LAST: hipLaunchKernelGGL((k_pass_batched<T, X_LAST, E>), g, b, 0, st, it, ar); break;
-    case C_PROP: hipLaunchKernelGGL((k_pass_batched<T, C_PROP, E>), g, b, 0, st, it, ar); break;
-    case XA_FIRST: hipLaunchKernelGGL((k_pass_batched<T, XA_FIRST, E>), g, b, 0, st, it, ar); break;
-    case XA_MID: hipLaunchKernelGGL((k_pass_batched<T, XA_MID, E>), g, b, 0, st, it, ar); break;
-    case XA_LAST: hipLaunchKernelGGL((k_pass_batched<T, XA_LAST, E>), g, b, 0, st, it, ar); break;
-    case C_ADJ: hipLaunchKernelGGL((k_pass_batched<T, C_ADJ, E>), g, b, 0, st, it, ar); break;
+    case X_FIRST: hipLaunchKernelGGL((k_pass_batched<T, X_FIRST, E, NMAX>), g, b, 0, st, it, ar); break;
+    case X_MID: hipLaunchKernelGGL((k_pass_batched<T, X_MID, E, NMAX>), g, b, 0, st, it, ar); break;
+    case X_LAST: hipLaunchKernelGGL((k_pass_batched<T, X_LAST, E, NMAX>), g, b, 0, st, it, ar); break;
+    case C_PROP: hipLaunchKernelGGL((k_pass_batched<T, C_PROP, E, NMAX>), g, b, 0, st, it, ar); break;
+    case XA_FIRST: hipLaunchKernelGGL((k_pass_batched<T, XA_FIRST, E, NMAX>), g, b, 0, st, it, ar); break;
+    case XA_MID: hipLaunchKernelGGL((k_pass_batched<T, XA_MID, E, NMAX>), g, b, 0, st, it, ar); break;
+    case XA_LAST: hipLaunchKernelGGL((k_pass_batched<T, XA_LAST, E, NMAX>), g, b, 0, st, it, ar); break;
+    case C_ADJ: hipLaunchKernelGGL((k_pass_batched<T, C_ADJ, E, NMAX>), g, b, 0, st, it, ar); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// nmax: the longest line among the launch's instances
+template <typename T, int E>
+hipError_t launch_batched_e(int kind, const int2* it, const PassArgs* ar, long nitems, int nmax, hipStream_t st) {
+  if constexpr (E == 12 || E == 24) {
+    if (nmax > 512) return launch_batched_nmax<T, E, 768>(kind, it, ar, nitems, st);
+  }
+  if (nmax > 512) return hipErrorInvalidValue;
+  return launch_batched_nmax<T, E, 512>(kind, it, ar, nitems, st);
 }
 
 }  // namespace sgp

@@ -62,6 +62,37 @@ def test_small_ensemble_batched_equals_unbatched_and_oracle(dtype, order):
         assert err <= tol
 
 
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_ensemble_with_192_and_768_batched_equals_unbatched(dtype):
+    # the 3 * 2^k sizes in one ensemble: 768^2 instances run the kernels sized for
+    # 768-point lines, the others those sized for lines up to 512 (the partitions of
+    # width pairs decide which); every instance bitwise equal to its unbatched run,
+    # the 768^2 one against the oracle
+    import torch
+    from paper_2603_25282_amd.sgp import SGP_OPT_BATCHED, Solver
+    base = I.ensemble_instances(seed=7, n128=1, n256=0, n384=1, L=12.0, order=2, tau=1e-3, steps=0)
+    insts = base + [I.with_(base[0], shape=(192, 192), name="e192"), I.with_(base[0], shape=(768, 768), L=24.0,
+                                                                             name="e768")]
+    nsteps = 18
+    print(f"case ensemble with 192^2 and 768^2, {dtype}", flush=True)
+    ens, psis = make(insts, dtype)
+    ens.build_propagator(1e-3, 2)
+    ens.step(psis, nsteps)
+    ens2, psis2 = make(insts, dtype)
+    ens2.build_propagator(1e-3, 2)
+    ens2.set_option(SGP_OPT_BATCHED, 0)
+    ens2.step(psis2, nsteps)
+    torch.cuda.synchronize()
+    for k, c in enumerate(insts):
+        assert np.array_equal(psis[k].cpu().numpy(), psis2[k].cpu().numpy()), f"instance {k} ({c.shape}) differs"
+    c = insts[-1]
+    ref = oracle.evolve(I.initial_state(c), c.L, c.params, 2, 1e-3, nsteps)
+    got = Solver.from_device_layout(psis[-1].cpu().numpy().astype(np.complex128))
+    err = rel_l2(got, ref)
+    print(f"  768^2 instance rel l2 {err:.3e}", flush=True)
+    assert err <= (1e-11 if dtype == "complex128" else 5e-5)
+
+
 def test_full_ensemble_workload_consistency():
     # The 96-instance workload (32 x 128^2, 48 x 256^2, 16 x 384^2), 40 TS2 steps:
     # batched == unbatched bitwise for every instance, finite, and one instance of
