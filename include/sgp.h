@@ -197,9 +197,9 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
  *   and drops the captured step graph; call it between steps, not concurrently
  *   with work on the context's stream.
  * sgp_get_plan: the current width of `axis`.
- * sgp_autotune: picks the fastest width per axis (one axis at a time, the others
- *   at their current best) by timing `steps` whole steps of sgp_step() per
- *   candidate, after one untimed call of `steps` steps per candidate.  psi_dev is
+ * sgp_autotune: picks the fastest combination of the axes' widths (every
+ *   combination, at most 9 in 2D and 27 in 3D) by timing `steps` steps of the
+ *   sgp_step path for each, after one untimed call of `steps` steps; psi_dev is
  *   a device state in the layout of sgp_step; it is advanced by every timed and
  *   untimed step (pass a scratch copy).  Needs the workspace and the propagator;
  *   the context time is left unchanged.  Writes the chosen widths to elems_out

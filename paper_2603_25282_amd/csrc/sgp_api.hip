@@ -517,9 +517,8 @@ int set_plan_impl(sgp_ctx* c, int axis, int e) {
   return SGP_OK;
 }
 
-// Autotuner: per axis in turn (the other axes at their current best), time `steps`
-// whole steps (the sgp_step path, graphs included) with every plan width of that
-// axis and keep the fastest.  psi is advanced by the timed steps; the context time
+// Autotuner: time `steps` whole steps (the sgp_step path, graphs included) for
+// every combination of the axes' plan widths and keep the fastest.  psi is advanced by the timed steps; the context time
 // is restored.
 template <typename T>
 int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_ms) {
@@ -544,21 +543,31 @@ int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_m
     *ms = (double)f / steps;
     return SGP_OK;
   };
+  // every combination of the axes' plan widths (at most 3 per axis: 9 in 2D, 27 in
+  // 3D); the plans of different axes interact through the passes' occupancy
   double best = 0.0;
   int rc = time_steps(&best);
-  for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) {
-    const int start = c->plan_e[ax];
-    int best_e = start;
-    for (int e : plan_widths(c->g.n[ax], (int)c->esize)) {
-      if (e == start) continue;
-      double ms = 0.0;
-      rc = set_plan_impl<T>(c, ax, e);
-      if (rc == SGP_OK) rc = time_steps(&ms);
-      if (rc != SGP_OK) break;
-      if (ms < best) { best = ms; best_e = e; }
-    }
-    if (rc == SGP_OK) rc = set_plan_impl<T>(c, ax, best_e);
-  }
+  std::vector<int> w[3];
+  for (int ax = 0; ax < 3; ++ax) w[ax] = ax < c->g.dim ? plan_widths(c->g.n[ax], (int)c->esize) : std::vector<int>{0};
+  int best_e[3] = {c->plan_e[0], c->plan_e[1], c->plan_e[2]};
+  const int start[3] = {c->plan_e[0], c->plan_e[1], c->plan_e[2]};
+  for (int ex : w[0])
+    for (int ey : w[1])
+      for (int ez : w[2]) {
+        if (rc != SGP_OK) break;
+        const int cand[3] = {ex, ey, ez};
+        bool same = true;
+        for (int ax = 0; ax < c->g.dim; ++ax) same = same && cand[ax] == start[ax];
+        if (same) continue;
+        for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, cand[ax]);
+        double ms = 0.0;
+        if (rc == SGP_OK) rc = time_steps(&ms);
+        if (rc == SGP_OK && ms < best) {
+          best = ms;
+          for (int ax = 0; ax < c->g.dim; ++ax) best_e[ax] = cand[ax];
+        }
+      }
+  for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, best_e[ax]);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->t = t_save;
