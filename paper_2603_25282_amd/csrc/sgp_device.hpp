@@ -138,6 +138,35 @@ struct Dft<6, SIGN, T> {
   }
 };
 
+// Length 12 = 4 * 3 by the prime-factor mapping (no inner twiddles): input
+// n = (3 n1 + 4 n2) mod 12, output k = (9 k1 + 4 k2) mod 12, so that
+// exp(2 pi i n k / 12) = exp(2 pi i n1 k1 / 4) exp(2 pi i n2 k2 / 3).
+template <int SIGN, typename T>
+struct Dft<12, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    // length-4 transforms over n1 for n2 = 0, 1, 2
+    cx<T> a[4] = {x[0], x[3], x[6], x[9]};
+    cx<T> b[4] = {x[4], x[7], x[10], x[1]};
+    cx<T> c[4] = {x[8], x[11], x[2], x[5]};
+    Dft<4, SIGN, T>::run(a);
+    Dft<4, SIGN, T>::run(b);
+    Dft<4, SIGN, T>::run(c);
+    // length-3 transforms over n2 for k1 = 0..3; k2 = 0, 1, 2 land at (9 k1 + 4 k2) mod 12
+    cx<T> z0[3] = {a[0], b[0], c[0]};
+    cx<T> z1[3] = {a[1], b[1], c[1]};
+    cx<T> z2[3] = {a[2], b[2], c[2]};
+    cx<T> z3[3] = {a[3], b[3], c[3]};
+    Dft<3, SIGN, T>::run(z0);
+    Dft<3, SIGN, T>::run(z1);
+    Dft<3, SIGN, T>::run(z2);
+    Dft<3, SIGN, T>::run(z3);
+    x[0] = z0[0]; x[4] = z0[1]; x[8] = z0[2];
+    x[9] = z1[0]; x[1] = z1[1]; x[5] = z1[2];
+    x[6] = z2[0]; x[10] = z2[1]; x[2] = z2[2];
+    x[3] = z3[0]; x[7] = z3[1]; x[11] = z3[2];
+  }
+};
+
 template <int SIGN, typename T>
 struct Dft<8, SIGN, T> {
   __device__ __forceinline__ static void run(cx<T>* x) {
@@ -311,11 +340,11 @@ template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = R
 // 384 = 3 * 2^7: E = 12 (default) and E = 24
 template <> struct Plan<384, 12> { using fwd = RadixList<6, 4, 4, 4>; using inv = RadixList<4, 4, 4, 6>; };
 template <> struct Plan<384, 24> { using fwd = RadixList<6, 8, 8>; using inv = RadixList<8, 8, 6>; };
-// 192 = 3 * 2^6 and 768 = 3 * 2^8: E = 12 (default) and E = 24
-template <> struct Plan<192, 12> { using fwd = RadixList<3, 4, 4, 4>; using inv = RadixList<4, 4, 4, 3>; };
+// 192 = 3 * 2^6 and 768 = 3 * 2^8: E = 12 (default) and E = 24 (radix 12: 4 x 3)
+template <> struct Plan<192, 12> { using fwd = RadixList<12, 4, 4>; using inv = RadixList<4, 4, 12>; };
 template <> struct Plan<192, 24> { using fwd = RadixList<3, 8, 8>; using inv = RadixList<8, 8, 3>; };
-template <> struct Plan<768, 12> { using fwd = RadixList<3, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 3>; };
-template <> struct Plan<768, 24> { using fwd = RadixList<3, 8, 8, 4>; using inv = RadixList<4, 8, 8, 3>; };
+template <> struct Plan<768, 12> { using fwd = RadixList<12, 4, 4, 4>; using inv = RadixList<4, 4, 4, 12>; };
+template <> struct Plan<768, 24> { using fwd = RadixList<12, 8, 8>; using inv = RadixList<8, 8, 12>; };
 
 // Twiddle-table entries of a plan direction: NS (R - 1) per pass with NS > 1 (each
 // entry is a (hi, lo) pair of cx<T>).

@@ -31,7 +31,7 @@ namespace sgp {
 // interleaved, one 8- or 16-byte LDS access each).
 template <int N> struct PadLine {
   static constexpr int extra = N == 512 ? 13 : N == 256 ? 13 : N == 128 ? 13 : N == 64 ? 5 : N == 384 ? 2
-                             : N == 768 ? 2 : N == 192 ? 15 : N == 32 ? 9 : N == 16 ? 1 : 1;
+                             : N == 768 ? 13 : N == 192 ? 5 : N == 32 ? 9 : N == 16 ? 1 : 1;
   static constexpr int size = N + N / 8 + extra;
 };
 
