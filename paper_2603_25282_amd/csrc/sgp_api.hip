@@ -1263,12 +1263,17 @@ template <typename F>
 hipError_t ens_fork_run(sgp_ensemble* e, hipStream_t st, F&& fn) {
   const size_t np = e->parts.size();
   hipError_t r = np > 1 ? ens_side_streams(e, np - 1) : hipSuccess;
-  if (np > 1 && r == hipSuccess) r = hipEventRecord(e->ev_fork, st);
-  for (size_t k = 1; k < np && r == hipSuccess; ++k) r = hipStreamWaitEvent(e->side[k - 1], e->ev_fork, 0);
-  for (size_t k = 0; k < np && r == hipSuccess; ++k) r = fn(e->parts[k], k == 0 ? st : e->side[k - 1]);
-  for (size_t k = 1; k < np && r == hipSuccess; ++k) {
-    r = hipEventRecord(e->ev_join[k - 1], e->side[k - 1]);
-    if (r == hipSuccess) r = hipStreamWaitEvent(st, e->ev_join[k - 1], 0);
+  if (r != hipSuccess) return r;
+  if (np > 1) r = hipEventRecord(e->ev_fork, st);
+  size_t forked = 1;  // streams that may hold work of this call (st always)
+  for (; forked < np && r == hipSuccess; ++forked) r = hipStreamWaitEvent(e->side[forked - 1], e->ev_fork, 0);
+  for (size_t k = 0; k < forked && r == hipSuccess; ++k) r = fn(e->parts[k], k == 0 ? st : e->side[k - 1]);
+  // join every forked side stream even after an error, so that st never runs
+  // ahead of work already queued on them; the first error is returned
+  for (size_t k = 1; k < forked; ++k) {
+    hipError_t q = hipEventRecord(e->ev_join[k - 1], e->side[k - 1]);
+    if (q == hipSuccess) q = hipStreamWaitEvent(st, e->ev_join[k - 1], 0);
+    if (r == hipSuccess) r = q;
   }
   return r;
 }
