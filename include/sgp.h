@@ -182,7 +182,8 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
 /* Register plans of the FFT line kernels.  Every pass along an axis of length n
  * transforms each (line, component) with n/E threads holding E elements each; E
  * fixes the radix sequence (E = 8: radix 8 with one radix-2/4 pass; E = 4: radix 4
- * with one radix-2 pass; E = 16: radix 8 with two butterflies per thread; 192,
+ * with one radix-2 pass; E = 16: radix 16 for 128 and 256, else radix 8 with two
+ * butterflies per thread; 192,
  * 384, 768: E = 12 (radix 12, 6 for 384, then radix 4) or, for SGP_C64 only,
  * E = 24 (radix 3, 6 for 384, 12 for 768, then radix 8))
  * and the block shape.  Every plan computes the same transform (results differ by

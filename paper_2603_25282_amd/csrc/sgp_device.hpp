@@ -167,6 +167,68 @@ struct Dft<12, SIGN, T> {
   }
 };
 
+// Length 16 = 4 x 4: length-4 transforms over n1 of x[4 n1 + n2], the inner
+// twiddles exp(SIGN 2 pi i n2 k1 / 16) (compensated constants in FP32), then
+// length-4 transforms over n2, landing at k1 + 4 k2.
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> w16_mul(cx<T> z, T crh, T crl, T cih, T cil) {
+  // z * (cr + SIGN i ci)
+  const T a = kmul<T>(crh, crl, z.re), b = kmul<T>(cih, cil, z.im);
+  const T c = kmul<T>(cih, cil, z.re), d = kmul<T>(crh, crl, z.im);
+  return SIGN > 0 ? mk<T>(a - b, c + d) : mk<T>(a + b, d - c);
+}
+
+template <int SIGN, typename T>
+struct Dft<16, SIGN, T> {
+  __device__ __forceinline__ static void run(cx<T>* x) {
+    const bool f32 = sizeof(T) == 4;
+    // cos(pi/8), sin(pi/8), sqrt(2)/2 as (hi, lo) pairs in FP32
+    const T ch = f32 ? T(0.92387950420379638671875) : T(0.92387953251128675612818318939678829);
+    const T cl = T(f32 ? 2.830749e-08 : 0.0);
+    const T sh = f32 ? T(0.3826834261417388916015625) : T(0.38268343236508977172845998403039887);
+    const T sl = T(f32 ? 6.2233507e-09 : 0.0);
+    const T hh = f32 ? T(0.707106769084930419921875) : T(0.70710678118654752440084436210484904);
+    const T hl = T(f32 ? 1.2101617e-08 : 0.0);
+    cx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      a[n2][0] = x[n2];
+      a[n2][1] = x[4 + n2];
+      a[n2][2] = x[8 + n2];
+      a[n2][3] = x[12 + n2];
+      Dft<4, SIGN, T>::run(a[n2]);
+    }
+    // twiddles exp(SIGN 2 pi i j / 16), j = n2 k1
+    a[1][1] = w16_mul<SIGN, T>(a[1][1], ch, cl, sh, sl);  // j = 1
+    a[1][2] = w16_mul<SIGN, T>(a[1][2], hh, hl, hh, hl);  // j = 2
+    a[1][3] = w16_mul<SIGN, T>(a[1][3], sh, sl, ch, cl);  // j = 3
+    a[2][1] = w16_mul<SIGN, T>(a[2][1], hh, hl, hh, hl);  // j = 2
+    a[2][2] = rot_quarter<SIGN>(a[2][2]);                  // j = 4
+    {                                                      // j = 6: -h + SIGN i h
+      const cx<T> t = w16_mul<SIGN, T>(a[2][3], hh, hl, hh, hl);
+      a[2][3] = rot_quarter<SIGN>(t);
+    }
+    a[3][1] = w16_mul<SIGN, T>(a[3][1], sh, sl, ch, cl);  // j = 3
+    {                                                      // j = 6
+      const cx<T> t = w16_mul<SIGN, T>(a[3][2], hh, hl, hh, hl);
+      a[3][2] = rot_quarter<SIGN>(t);
+    }
+    {                                                      // j = 9: -(c + SIGN i s)
+      const cx<T> t = w16_mul<SIGN, T>(a[3][3], ch, cl, sh, sl);
+      a[3][3] = mk<T>(-t.re, -t.im);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> z[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, SIGN, T>::run(z);
+      x[k1] = z[0];
+      x[k1 + 4] = z[1];
+      x[k1 + 8] = z[2];
+      x[k1 + 12] = z[3];
+    }
+  }
+};
+
 template <int SIGN, typename T>
 struct Dft<8, SIGN, T> {
   __device__ __forceinline__ static void run(cx<T>* x) {
@@ -332,10 +394,11 @@ template <> struct Plan<64, 4> { using fwd = RadixList<4, 4, 4>; using inv = Rad
 template <> struct Plan<128, 4> { using fwd = RadixList<2, 4, 4, 4>; using inv = RadixList<4, 4, 4, 2>; };
 template <> struct Plan<256, 4> { using fwd = RadixList<4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4>; };
 template <> struct Plan<512, 4> { using fwd = RadixList<2, 4, 4, 4, 4>; using inv = RadixList<4, 4, 4, 4, 2>; };
-// E = 16: the E = 8 radices, two butterflies per thread and pass
+// E = 16: radix 16 for 128 (8.16) and 256 (16.16); for 64 and 512 the E = 8
+// radices, two butterflies per thread and pass
 template <> struct Plan<64, 16> { using fwd = RadixList<8, 8>; using inv = RadixList<8, 8>; };
-template <> struct Plan<128, 16> { using fwd = RadixList<2, 8, 8>; using inv = RadixList<8, 8, 2>; };
-template <> struct Plan<256, 16> { using fwd = RadixList<4, 8, 8>; using inv = RadixList<8, 8, 4>; };
+template <> struct Plan<128, 16> { using fwd = RadixList<8, 16>; using inv = RadixList<16, 8>; };
+template <> struct Plan<256, 16> { using fwd = RadixList<16, 16>; using inv = RadixList<16, 16>; };
 template <> struct Plan<512, 16> { using fwd = RadixList<8, 8, 8>; using inv = RadixList<8, 8, 8>; };
 // 384 = 3 * 2^7: E = 12 (default) and E = 24
 template <> struct Plan<384, 12> { using fwd = RadixList<6, 4, 4, 4>; using inv = RadixList<4, 4, 4, 6>; };
