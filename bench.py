@@ -31,7 +31,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--dtype", default="complex64", choices=["complex64", "complex128"])
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "ensemble", "paper-eff"])
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "3d-256", "ensemble", "paper-eff"],
+                    help="2d: 512^2 TS4 (default); 3d: 128^3 TS4; 3d-256: the 3d workload at 256^3 "
+                         "(a state larger than the Infinity Cache; forward and pass timings only); "
+                         "ensemble: 96 grids; paper-eff: the paper's timing table")
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=50)
@@ -64,7 +67,13 @@ def main():
     from paper_2603_25282_amd import inputs as I
     from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, Solver
 
-    cfg = I.C2 if a.workload == "2d" else I.C3
+    cfg = {"2d": I.C2, "3d": I.C3, "3d-256": I.C3_256}[a.workload]
+    if a.workload == "3d-256":
+        # forward and per-pass timings only: the checkpoint store of the fwd+adjoint
+        # leg would hold tens of states of 640 MiB, and the oracle sample would take
+        # minutes per step
+        a.adjoint_steps = a.lab_steps = 0
+        a.no_cpu_baseline = True
     esz = 8 if a.dtype == "complex64" else 16
     npts = cfg.points
     psi0 = I.initial_state(cfg)
@@ -77,6 +86,7 @@ def main():
         s.set_plan([int(x) for x in a.plan.split(",")])
     plan = s.get_plan()
 
+    mass0 = float(s.observables(psi)[0])
     # warmup (also captures the step graph)
     s.step(psi, a.warmup)
     torch.cuda.synchronize()
@@ -93,6 +103,8 @@ def main():
     region_ms = ev0.elapsed_time(ev1)
     gps = npts * a.steps / elapsed
     finite = bool(torch.isfinite(torch.view_as_real(psi)).all().item())
+    # the flow conserves mass exactly; what changes is rounding
+    mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
 
     # dominant kernel and its average launch duration in the timed region: each
     # pass's share of a step from event pairs around its launches inside the pass
@@ -132,8 +144,7 @@ def main():
             traffic = None
 
     out = {
-        "metric": "5-comp grid-point-steps/s fwd (2D 512^2 TS4)" if cfg.dim == 2 else
-                  "5-comp grid-point-steps/s fwd (3D 128^3 TS4)",
+        "metric": f"5-comp grid-point-steps/s fwd ({cfg.dim}D {cfg.shape[0]}^{cfg.dim} TS{cfg.order})",
         "value": gps,
         "unit": "gp-steps/s",
         "n_gpus": 1,
@@ -146,7 +157,8 @@ def main():
         "dtype": "f32" if a.dtype == "complex64" else "f64",
         "data": "synthetic (seeded Gaussian + noise initial state)",
         "config": {"workload": cfg.name, "grid": list(cfg.shape), "L": cfg.L, "scheme": f"TS{cfg.order}",
-                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "plan": plan, "finite": finite},
+                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "plan": plan, "finite": finite,
+                   "mass_rel_change": mass_change},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,

@@ -161,6 +161,17 @@ SOC_II = Config("paper-soc-case2", (768, 768), 24.0, (243.0, 12.1, -13.0, 0.2, 0
 CONFIGS = {c.name: c for c in (C1, C2, C3, C5, ACC2D, ACC3D)}
 
 
+def _c3_256():
+    # the 3D workload above at 256^3 on the same domain (h = 1/16): a 640 MiB
+    # complex64 state, larger than the 256 MB Infinity Cache, so every pass streams
+    # from and to HBM
+    return Config("3d-256-ts4-hbm", (256, 256, 256), C3.L, C3.params, order=C3.order, tau=C3.tau,
+                  steps=C3.steps, seed=C3.seed, init=C3.init, extra=dict(C3.extra))
+
+
+C3_256 = _c3_256()
+
+
 def with_(cfg: Config, **kw):
     d = dict(cfg.__dict__)
     d.update(kw)
