@@ -65,7 +65,9 @@ enum { SGP_TS2 = 2, SGP_TS4 = 4, SGP_TS6 = 6 };
 typedef struct sgp_ctx sgp_ctx;
 
 /* Grid: dim = 2 or 3; n[0..dim-1] = points along x, y[, z]; L[] = half-widths.
- * Supported n per axis: 16, 32, 64, 128, 256, 512 and 192, 384, 768 (3 * 2^k). */
+ * Supported n per axis: 16, 32, 64, 128, 256, 512 and 192, 384, 768 (3 * 2^k),
+ * with at most 2^31 - 1 state elements in all (5 n_x n_y n_z: every 3D grid up to
+ * 768 x 768 x 512 fits, 768^3 does not); sgp_create returns SGP_ERR_ARG beyond. */
 typedef struct {
   int dim;
   int n[3];

@@ -809,6 +809,14 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
                                             " (supported: 16, 32, 64, 128, 192, 256, 384, 512, 768)");
     if (!(grid->L[i] > 0.0) || !std::isfinite(grid->L[i])) return fail(nullptr, SGP_ERR_ARG, "L must be > 0");
   }
+  {
+    // the kernels address the state with 32-bit element offsets
+    long long elems = 5;
+    for (int i = 0; i < grid->dim; ++i) elems *= grid->n[i];
+    if (elems > 2147483647LL)
+      return fail(nullptr, SGP_ERR_ARG, "grid too large: 5 n_x n_y n_z = " + std::to_string(elems) +
+                                            " state elements, at most 2^31 - 1 are supported");
+  }
   const double* pv = &params->c0;
   for (int i = 0; i < 8; ++i)
     if (!std::isfinite(pv[i])) return fail(nullptr, SGP_ERR_ARG, "non-finite parameter");

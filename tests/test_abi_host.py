@@ -46,10 +46,18 @@ def _create(dim=2, n=(64, 64, 1), L=(8.0, 8.0, 1.0), params=(1, 1, 1, 0.5, 0.5, 
 def test_create_validates_arguments():
     L = sgp.lib()
     for kw in (dict(n=(48, 64, 1)), dict(n=(64, 1024, 1)), dict(L=(0.0, 8.0, 1.0)), dict(dim=4),
-               dict(params=(1, 1, float("nan"), 0, 0, 1, 1, 1)), dict(dtype=7)):
+               dict(params=(1, 1, float("nan"), 0, 0, 1, 1, 1)), dict(dtype=7),
+               # 5 x 768^3 state elements do not fit the kernels' 32-bit offsets
+               dict(dim=3, n=(768, 768, 768), L=(8.0, 8.0, 8.0))):
         rc, ctx = _create(**kw)
         assert rc == -1, kw
         assert L.sgp_last_error(None)
+    assert b"too large" in L.sgp_last_error(None)
+    # the largest grids that fit are accepted
+    for n in ((768, 768, 512), (512, 512, 512)):
+        rc, ctx = _create(dim=3, n=n, L=(8.0, 8.0, 8.0))
+        assert rc == 0, n
+        L.sgp_destroy(ctx)
     rc, ctx = _create()
     assert rc == 0
     nb = ctypes.c_size_t()
