@@ -170,6 +170,28 @@ def main():
     out["bytes_model"] = {"bytes_per_gp_step": sum(per_point[k] * launches_per_step[k] for k in passes),
                           "GB_per_s": sum(per_point[k] * launches_per_step[k] for k in passes) * gps / 1e9}
 
+    # the plain-copy ceiling at this state size: device copies of the state back and
+    # forth between two buffers (each copy reads what the previous one wrote, as the
+    # passes do), timed with events on torch's stream; 2 x state bytes per copy
+    cp = [psi.clone(), torch.empty_like(psi)]
+    for i in range(6):
+        cp[(i + 1) % 2].copy_(cp[i % 2])
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ncp = 50
+    c0.record()
+    for i in range(ncp):
+        cp[(i + 1) % 2].copy_(cp[i % 2])
+    c1.record()
+    torch.cuda.synchronize()
+    cms = c0.elapsed_time(c1) / ncp
+    cbytes = 2 * psi.numel() * psi.element_size()
+    out["roofline"]["copy_ceiling"] = {
+        "GB_per_s": cbytes / (cms * 1e-3) / 1e9, "ms_per_copy": cms, "bytes_per_copy": cbytes,
+        "dominant_kernel_frac_of_copy": achieved / (cbytes / (cms * 1e-3) / 1e9),
+        "what": "ping-pong device copy of the state (torch copy_), the rate a pass that only moved "
+                "its bytes would reach at this size"}
+    del cp
+
     if a.adjoint_steps > 0:
         # forward with checkpoints every K steps + backward (recompute with stores and
         # reverse sweep), the loss gradient being a fixed random direction
