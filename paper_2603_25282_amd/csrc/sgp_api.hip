@@ -1246,6 +1246,16 @@ hipError_t ens_build_items(sgp_ensemble* e) {
         for (long t = 0; t < nt; ++t) items.push_back(make_int2(i, (int)t));
       }
       P.n[ax] = (long)items.size() - P.off[ax];
+      // block b of a launch runs on XCD b % 8: give each XCD one contiguous range of
+      // the partition's items (XCD j gets n/8 items, one more when j < n % 8), so
+      // neighbouring tiles, which share cache lines, share that XCD's L2
+      const long n = P.n[ax];
+      std::vector<int2> perm(n);
+      for (long b = 0; b < n; ++b) {
+        const long j = b % 8, start = j * (n / 8) + std::min(j, n % 8);
+        perm[b] = items[P.off[ax] + start + b / 8];
+      }
+      std::copy(perm.begin(), perm.end(), items.begin() + P.off[ax]);
     }
     hipError_t r = hipMemcpyAsync(e->ws + e->off_items[ax], items.data(), sizeof(int2) * items.size(),
                                   hipMemcpyHostToDevice, e->st);
