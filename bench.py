@@ -107,10 +107,9 @@ def main():
     mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
 
     # dominant kernel and its average launch duration in the timed region: each
-    # pass's share of a step from event pairs around its launches inside the pass
-    # sequence of a step (on a scratch copy of the state; the event overhead is
-    # common to all passes), times the event-timed step; back-to-back launches of
-    # one pass for reference
+    # pass's share of a step from the start/end events stamped by the dispatches of
+    # its launches inside whole steps (on a scratch copy of the state), times the
+    # event-timed step; back-to-back launches of one pass for reference
     scratch = psi.clone()
     passes = {"xpass": SGP_PASS_X, "ypass": SGP_PASS_Y} if cfg.dim == 2 else \
         {"xpass": SGP_PASS_X, "ypass_fwd": SGP_PASS_Y, "zpass": SGP_PASS_Z, "ypass_inv": SGP_PASS_YINV}
@@ -123,8 +122,8 @@ def main():
     launches_per_step = {"xpass": 3, "ypass": 3, "ypass_fwd": 3, "zpass": 3, "ypass_inv": 3}
     pair, iso = {}, {}
     for name, pk in passes.items():
-        s.time_pass(scratch, pk, 10, in_step=True)
-        pair[name] = s.time_pass(scratch, pk, a.pass_reps, in_step=True)
+        s.time_pass(scratch, pk, 4, in_steps=True)
+        pair[name] = s.time_pass(scratch, pk, a.pass_reps, in_steps=True)
         iso[name] = s.time_pass(scratch, pk, a.pass_reps)
     step_ms = region_ms / a.steps
     tot = sum(pair[k] * launches_per_step[k] for k in passes)
@@ -162,9 +161,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,
-                     "pass_ms": times, "pass_ms_event_pairs": pair, "pass_ms_back_to_back": iso,
-                     "timing": "avg_launch_ms = event-timed step x the pass's share of a step (event pairs around "
-                               "its launches in step order) / its launches per step"},
+                     "pass_ms": times, "pass_ms_in_step": pair, "pass_ms_back_to_back": iso,
+                     "timing": "avg_launch_ms = event-timed step x the pass's share of a step / its launches per "
+                               "step; shares from pass_ms_in_step, the mean duration of the pass's launches inside "
+                               "pass_reps steps of the step schedule, each timed by start/end events that its "
+                               "dispatch stamps"},
     }
     # whole-step bandwidth of the bytes model (R round trips of the state per step)
     out["bytes_model"] = {"bytes_per_gp_step": sum(per_point[k] * launches_per_step[k] for k in passes),

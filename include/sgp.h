@@ -176,9 +176,13 @@ int sgp_set_time(sgp_ctx* ctx, double t);
  * With pass | SGP_TIME_IN_STEP the passes of a substep run in step order (2D:
  * y, X; 3D: y, z, inverse y, X) `reps` times and only the launches of the named
  * pass are timed, each between its own pair of events (its data then comes from
- * the previous pass, as inside sgp_step).  Requires a built propagator.
- * Synchronous. */
-enum { SGP_TIME_IN_STEP = 256 };
+ * the previous pass, as inside sgp_step).  With pass | SGP_TIME_STEPS, `reps` (>= 2)
+ * whole steps of sgp_step's schedule run (launched without the graph; psi
+ * advances, the context time is restored) and every launch of the named pass in
+ * them is timed by a start/end event pair that its dispatch stamps (pass 0: the
+ * X-passes between two linear substeps); the rotating frame only.  Requires a
+ * built propagator.  Synchronous. */
+enum { SGP_TIME_IN_STEP = 256, SGP_TIME_STEPS = 512 };
 int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_ms);
 
 /* Register plans of the FFT line kernels.  Every pass along an axis of length n

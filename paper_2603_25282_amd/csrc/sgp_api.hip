@@ -110,6 +110,12 @@ struct sgp_ctx {
   int gsteps = 0;
   bool use_graph = true;
 
+  // measurement hook (sgp_time_pass with SGP_TIME_STEPS): while it is set, every
+  // launch of pass `tev_pass` takes the next event pair of tev
+  std::vector<hipEvent_t> tev;
+  int tev_pass = -1;
+  size_t tev_used = 0;
+
   long npts() const { return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1); }
   int elems(int axis) const { return plan_e[axis]; }
   void* at(size_t off) const { return ws + off; }
@@ -127,6 +133,13 @@ int fail(sgp_ctx* c, int code, const std::string& msg) {
 
 int hip_fail(sgp_ctx* c, hipError_t e, const char* where) {
   return fail(c, SGP_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// The next event pair for a launch of pass `pass` (numbered as in sgp_time_pass)
+// while a step timing runs; null otherwise.
+const hipEvent_t* timing_events(sgp_ctx* c, int pass) {
+  if (pass < 0 || pass != c->tev_pass || 2 * c->tev_used + 1 >= c->tev.size()) return nullptr;
+  return &c->tev[2 * c->tev_used++];
 }
 
 // TS4 coefficients (Sec. 3.3): a1 = a4, a2 = a3 on the nonlinear flow; b1 = b3, b2 on
@@ -217,18 +230,21 @@ void column_geometry(const sgp_ctx* c, int axis, PassArgs& a) {
 }
 
 template <typename T>
-hipError_t run_xpass(sgp_ctx* c, hipStream_t st, int mode, void* psi, double d, int clock_mode, double s_arg) {
+hipError_t run_xpass(sgp_ctx* c, hipStream_t st, int mode, void* psi, double d, int clock_mode, double s_arg,
+                     const hipEvent_t* ev = nullptr) {
   PassArgs a = base_args(c);
   a.tw_fwd = c->at(c->off_tw[0][0]);
   a.tw_inv = c->at(c->off_tw[0][1]);
   a.d = d;
   a.s_arg = s_arg;
   a.clock_mode = clock_mode;
-  return launch_pass<T>(mode, psi, a, c->g.n[0], c->elems(0), st);
+  if (!ev) ev = timing_events(c, mode == X_MID ? 0 : -1);
+  return launch_pass<T>(mode, psi, a, c->g.n[0], c->elems(0), st, ev);
 }
 
 template <typename T>
-hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi, int table, double d) {
+hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi, int table, double d,
+                       const hipEvent_t* ev = nullptr) {
   PassArgs a = base_args(c);
   column_geometry(c, axis, a);
   a.cs = c->at(c->off_cs[table]);
@@ -237,7 +253,14 @@ hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi
   a.kin_l = c->at(c->off_kin[table][axis]);
   a.d = d;
   a.advance_clock = (mode == C_PROP) ? 1 : 0;
-  return launch_pass<T>(mode, psi, a, c->g.n[axis], c->elems(axis), st);
+  if (!ev) {
+    int pid = -1;
+    if (axis == 1 && (mode == C_PROP || mode == C_FWD)) pid = 1;
+    else if (axis == 2 && mode == C_PROP) pid = 2;
+    else if (axis == 1 && mode == C_INV) pid = 3;
+    ev = timing_events(c, pid);
+  }
+  return launch_pass<T>(mode, psi, a, c->g.n[axis], c->elems(axis), st, ev);
 }
 
 // Store-mode and adjoint variants of the passes.
@@ -437,18 +460,21 @@ int step_impl(sgp_ctx* c, void* psi, long nsteps) {
 // stream, bracketed by HIP events.  pass: 0 X-pass (mid form), 1 linear pass along
 // y (2D: with the propagator; 3D: forward y), 2 z-pass with the propagator (3D),
 // 3 inverse y-pass (3D).
+// ev: null, or an event pair that the dispatch stamps with the kernel's start and end.
 template <typename T>
-hipError_t launch_timed_pass(sgp_ctx* c, void* psi, int pass, bool first) {
+hipError_t launch_timed_pass(sgp_ctx* c, void* psi, int pass, bool first, const hipEvent_t* ev = nullptr) {
   // X-pass as inside a step: the clock from the device slots (set by the first launch)
-  if (pass == 0) return run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], first ? CLOCK_ARG : CLOCK_DEVICE, c->t);
-  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0);
-  if (pass == 2) return run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0);
-  return run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0);
+  if (pass == 0)
+    return run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], first ? CLOCK_ARG : CLOCK_DEVICE, c->t, ev);
+  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0, ev);
+  if (pass == 2) return run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0, ev);
+  return run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0, ev);
 }
 
 // In-step timing: reps rounds of the passes of one linear + nonlinear substep in
-// step order (2D: y, X; 3D: y, z, inverse y, X), an event pair around every launch
-// of the timed pass; the average of those durations.
+// step order (2D: y, X; 3D: y, z, inverse y, X); every launch of the timed pass
+// carries an event pair that its dispatch stamps with the kernel's start and end
+// (no marker packets between the kernels); the average of those durations.
 template <typename T>
 int time_pass_in_step(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   const std::vector<int> order = c->g.dim == 2 ? std::vector<int>{1, 0} : std::vector<int>{1, 2, 3, 0};
@@ -458,10 +484,8 @@ int time_pass_in_step(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms)
   bool first_x = true;
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     for (int p : order) {
-      if (p == pass) e = hipEventRecord(ev[2 * r], c->st);
-      if (e == hipSuccess) e = launch_timed_pass<T>(c, psi, p, p == 0 && first_x);
+      e = launch_timed_pass<T>(c, psi, p, p == 0 && first_x, p == pass ? &ev[2 * r] : nullptr);
       if (p == 0) first_x = false;
-      if (e == hipSuccess && p == pass) e = hipEventRecord(ev[2 * r + 1], c->st);
       if (e != hipSuccess) break;
     }
   double total = 0.0;
@@ -496,6 +520,48 @@ int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(c, e, "pass timing");
   *avg_ms = (double)ms / reps;
+  return SGP_OK;
+}
+
+// Timing inside real steps: `nsteps` steps of sgp_step's schedule, launched without
+// the graph (the same kernels in the same order); every launch of the named pass
+// carries an event pair that its dispatch stamps with the kernel's start and end.
+// psi advances nsteps steps; the context time is restored.
+template <typename T>
+int time_pass_steps(sgp_ctx* c, void* psi, int pass, int nsteps, double* avg_ms) {
+  c->tev.assign(2 * (12 * (size_t)nsteps + 8), nullptr);  // more pairs than launches of one pass
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < c->tev.size() && e == hipSuccess; ++i) e = hipEventCreate(&c->tev[i]);
+  int rc = SGP_OK;
+  size_t used = 0;
+  if (e == hipSuccess) {
+    const double t_save = c->t;
+    const bool g_save = c->use_graph;
+    c->use_graph = false;
+    c->tev_pass = pass;
+    c->tev_used = 0;
+    rc = step_impl<T>(c, psi, nsteps);
+    used = c->tev_used;
+    c->tev_pass = -1;
+    c->use_graph = g_save;
+    c->t = t_save;
+  }
+  double total = 0.0;
+  if (e == hipSuccess && rc == SGP_OK && used > 0) {
+    e = hipEventSynchronize(c->tev[2 * used - 1]);
+    for (size_t i = 0; i < used && e == hipSuccess; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]);
+      total += ms;
+    }
+  }
+  for (hipEvent_t x : c->tev)
+    if (x) (void)hipEventDestroy(x);
+  c->tev.clear();
+  if (e != hipSuccess) return hip_fail(c, e, "pass timing");
+  if (rc != SGP_OK) return rc;
+  if (used == 0) return fail(c, SGP_ERR_ARG, "the timed steps launch no such pass");
+  *avg_ms = total / (double)used;
   return SGP_OK;
 }
 
@@ -972,11 +1038,18 @@ int sgp_set_time(sgp_ctx* c, double t) {
 
 int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   if (!c || !psi || !avg_ms || reps < 1) return fail(c, SGP_ERR_ARG, "bad argument");
-  const int kind = pass & ~SGP_TIME_IN_STEP;
-  if (kind < 0 || kind > 3 || (c->g.dim == 2 && kind > 1) || (pass & ~(SGP_TIME_IN_STEP | 3)))
+  const int kind = pass & 3;
+  if ((c->g.dim == 2 && kind > 1) || (pass & ~(SGP_TIME_IN_STEP | SGP_TIME_STEPS | 3)) ||
+      ((pass & SGP_TIME_IN_STEP) && (pass & SGP_TIME_STEPS)))
     return fail(c, SGP_ERR_ARG, "no such pass");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
+  if (pass & SGP_TIME_STEPS) {
+    if (reps < 2) return fail(c, SGP_ERR_ARG, "SGP_TIME_STEPS needs at least 2 steps");
+    if (c->frame == SGP_FRAME_LAB) return fail(c, SGP_ERR_STATE, "SGP_TIME_STEPS times the rotating-frame step");
+    return c->dtype == SGP_C64 ? time_pass_steps<float>(c, psi, kind, reps, avg_ms)
+                               : time_pass_steps<double>(c, psi, kind, reps, avg_ms);
+  }
   return c->dtype == SGP_C64 ? time_pass_impl<float>(c, psi, pass, reps, avg_ms)
                              : time_pass_impl<double>(c, psi, pass, reps, avg_ms);
 }

@@ -7,7 +7,7 @@
 namespace sgp {
 
 #define SGP_EXTERN(TT, EE)                                                                            \
-  extern template hipError_t launch_pass_e<TT, EE>(int, void*, const PassArgs&, int, hipStream_t);   \
+  extern template hipError_t launch_pass_e<TT, EE>(int, void*, const PassArgs&, int, hipStream_t, const hipEvent_t*);   \
   extern template hipError_t launch_obs_e<TT, EE>(int, const void*, const PassArgs&, int, double*, hipStream_t);
 SGP_EXTERN(float, 4) SGP_EXTERN(float, 8) SGP_EXTERN(float, 12) SGP_EXTERN(float, 16) SGP_EXTERN(float, 24)
 SGP_EXTERN(double, 4) SGP_EXTERN(double, 8) SGP_EXTERN(double, 12) SGP_EXTERN(double, 16) SGP_EXTERN(double, 24)
@@ -19,14 +19,14 @@ SGP_EXTERN_B(double, 4) SGP_EXTERN_B(double, 8) SGP_EXTERN_B(double, 12) SGP_EXT
 #undef SGP_EXTERN_B
 
 template <typename T>
-hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st) {
+hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st, const hipEvent_t* ev) {
   if (!plan_ok(n, e, (int)sizeof(T))) return hipErrorInvalidValue;
   switch (e) {
-    case 4: return launch_pass_e<T, 4>(kind, psi, a, n, st);
-    case 8: return launch_pass_e<T, 8>(kind, psi, a, n, st);
-    case 12: return launch_pass_e<T, 12>(kind, psi, a, n, st);
-    case 16: return launch_pass_e<T, 16>(kind, psi, a, n, st);
-    case 24: return launch_pass_e<T, 24>(kind, psi, a, n, st);
+    case 4: return launch_pass_e<T, 4>(kind, psi, a, n, st, ev);
+    case 8: return launch_pass_e<T, 8>(kind, psi, a, n, st, ev);
+    case 12: return launch_pass_e<T, 12>(kind, psi, a, n, st, ev);
+    case 16: return launch_pass_e<T, 16>(kind, psi, a, n, st, ev);
+    case 24: return launch_pass_e<T, 24>(kind, psi, a, n, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -77,8 +77,8 @@ hipError_t launch_pass_batched(int kind, int e, const void* items, const void* a
 
 template hipError_t launch_pass_batched<float>(int, int, const void*, const void*, long, int, hipStream_t);
 template hipError_t launch_pass_batched<double>(int, int, const void*, const void*, long, int, hipStream_t);
-template hipError_t launch_pass<float>(int, void*, const PassArgs&, int, int, hipStream_t);
-template hipError_t launch_pass<double>(int, void*, const PassArgs&, int, int, hipStream_t);
+template hipError_t launch_pass<float>(int, void*, const PassArgs&, int, int, hipStream_t, const hipEvent_t*);
+template hipError_t launch_pass<double>(int, void*, const PassArgs&, int, int, hipStream_t, const hipEvent_t*);
 template hipError_t launch_obs<float>(int, const void*, const PassArgs&, int, int, double*, hipStream_t);
 template hipError_t launch_obs<double>(int, const void*, const PassArgs&, int, int, double*, hipStream_t);
 template hipError_t launch_build_tables<float>(void*, void*, void*, void*, const int*, const double*, int, double,

@@ -88,8 +88,10 @@ constexpr int obs_lines_per_block(int n, int e) {
   return w;
 }
 
+// ev: null, or a start / end event pair stamped by the kernel's dispatch
 template <typename T>
-hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st);
+hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hipStream_t st,
+                       const hipEvent_t* ev = nullptr);
 template <typename T>
 hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e, double* part, hipStream_t st);
 template <typename T>
@@ -106,7 +108,7 @@ hipError_t launch_pass_batched(int kind, int e, const void* items, const void* a
 
 // per-plan-width launchers, each (T, E) compiled in its own translation unit
 template <typename T, int E>
-hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st);
+hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st, const hipEvent_t* ev);
 template <typename T, int E>
 hipError_t launch_obs_e(int kind, const void* psi, const PassArgs& a, int n, double* part, hipStream_t st);
 

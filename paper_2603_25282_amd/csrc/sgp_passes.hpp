@@ -20,6 +20,8 @@
 // (components innermost), every thread updates whole points from the tile, and
 // the FFT threads read their elements back.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "sgp_device.hpp"
 #include "sgp_kernels.hpp"
 
@@ -711,33 +713,39 @@ struct Geo {
   static constexpr int NT = W * 5 * TL;
 };
 
+// ev: null, or two events that the dispatch itself stamps with the kernel's start
+// and end (timing without marker packets between the kernels).
 template <typename T, int N, int E, int KIND>
-static hipError_t pass_n(cx<T>* psi, const PassArgs& a, hipStream_t st) {
+static hipError_t pass_n(cx<T>* psi, const PassArgs& a, hipStream_t st, const hipEvent_t* ev) {
   constexpr int W = Geo<N, E>::W;
   constexpr bool XL = KindInfo<KIND>::XL;
   long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
-  hipLaunchKernelGGL((k_pass<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(Geo<N, E>::NT), 0, st, psi, a);
+  if (ev)
+    hipExtLaunchKernelGGL((k_pass<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(Geo<N, E>::NT), 0, st, ev[0],
+                          ev[1], 0, psi, a);
+  else
+    hipLaunchKernelGGL((k_pass<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(Geo<N, E>::NT), 0, st, psi, a);
   return hipGetLastError();
 }
 
 template <typename T, int N, int E>
-static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t st) {
+static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t st, const hipEvent_t* ev) {
   switch (kind) {
-    case X_FIRST: return pass_n<T, N, E, X_FIRST>(psi, a, st);
-    case X_MID: return pass_n<T, N, E, X_MID>(psi, a, st);
-    case X_LAST: return pass_n<T, N, E, X_LAST>(psi, a, st);
-    case X_NLONLY: return pass_n<T, N, E, X_NLONLY>(psi, a, st);
-    case C_PROP: return pass_n<T, N, E, C_PROP>(psi, a, st);
-    case C_FWD: return pass_n<T, N, E, C_FWD>(psi, a, st);
-    case C_INV: return pass_n<T, N, E, C_INV>(psi, a, st);
-    case XA_FIRST: return pass_n<T, N, E, XA_FIRST>(psi, a, st);
-    case XA_MID: return pass_n<T, N, E, XA_MID>(psi, a, st);
-    case XA_LAST: return pass_n<T, N, E, XA_LAST>(psi, a, st);
-    case C_ADJ: return pass_n<T, N, E, C_ADJ>(psi, a, st);
-    case X_SHEAR: return pass_n<T, N, E, X_SHEAR>(psi, a, st);
-    case C_SHEAR: return pass_n<T, N, E, C_SHEAR>(psi, a, st);
-    case X_FWD: return pass_n<T, N, E, X_FWD>(psi, a, st);
-    case X_INV: return pass_n<T, N, E, X_INV>(psi, a, st);
+    case X_FIRST: return pass_n<T, N, E, X_FIRST>(psi, a, st, ev);
+    case X_MID: return pass_n<T, N, E, X_MID>(psi, a, st, ev);
+    case X_LAST: return pass_n<T, N, E, X_LAST>(psi, a, st, ev);
+    case X_NLONLY: return pass_n<T, N, E, X_NLONLY>(psi, a, st, ev);
+    case C_PROP: return pass_n<T, N, E, C_PROP>(psi, a, st, ev);
+    case C_FWD: return pass_n<T, N, E, C_FWD>(psi, a, st, ev);
+    case C_INV: return pass_n<T, N, E, C_INV>(psi, a, st, ev);
+    case XA_FIRST: return pass_n<T, N, E, XA_FIRST>(psi, a, st, ev);
+    case XA_MID: return pass_n<T, N, E, XA_MID>(psi, a, st, ev);
+    case XA_LAST: return pass_n<T, N, E, XA_LAST>(psi, a, st, ev);
+    case C_ADJ: return pass_n<T, N, E, C_ADJ>(psi, a, st, ev);
+    case X_SHEAR: return pass_n<T, N, E, X_SHEAR>(psi, a, st, ev);
+    case C_SHEAR: return pass_n<T, N, E, C_SHEAR>(psi, a, st, ev);
+    case X_FWD: return pass_n<T, N, E, X_FWD>(psi, a, st, ev);
+    case X_INV: return pass_n<T, N, E, X_INV>(psi, a, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -768,11 +776,11 @@ static hipError_t obs_kind(int kind, const cx<T>* psi, const PassArgs& a, double
   X(16, E) X(32, E) X(64, E) X(128, E) X(192, E) X(256, E) X(384, E) X(512, E) X(768, E)
 
 template <typename T, int E>
-hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st) {
+hipError_t launch_pass_e(int kind, void* psi, const PassArgs& a, int n, hipStream_t st, const hipEvent_t* ev) {
   cx<T>* p = reinterpret_cast<cx<T>*>(psi);
 #define SGP_CASE(NN, EE) \
   case NN:               \
-    if constexpr (plan_ok(NN, EE, (int)sizeof(T))) return pass_kind<T, NN, EE>(kind, p, a, st); \
+    if constexpr (plan_ok(NN, EE, (int)sizeof(T))) return pass_kind<T, NN, EE>(kind, p, a, st, ev); \
     break;
   switch (n) { SGP_FOR_PLAN_N(E, SGP_CASE) default: break; }
 #undef SGP_CASE

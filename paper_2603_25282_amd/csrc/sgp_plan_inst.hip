@@ -8,7 +8,8 @@
 #endif
 
 namespace sgp {
-template hipError_t launch_pass_e<SGP_INST_T, SGP_INST_E>(int, void*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_pass_e<SGP_INST_T, SGP_INST_E>(int, void*, const PassArgs&, int, hipStream_t,
+                                                           const hipEvent_t*);
 template hipError_t launch_obs_e<SGP_INST_T, SGP_INST_E>(int, const void*, const PassArgs&, int, double*,
                                                          hipStream_t);
 template hipError_t launch_batched_e<SGP_INST_T, SGP_INST_E>(int, const int2*, const PassArgs*, long, int,

@@ -22,6 +22,7 @@ SGP_TS2, SGP_TS4, SGP_TS6 = 2, 4, 6
 SGP_PASS_X, SGP_PASS_Y, SGP_PASS_Z, SGP_PASS_YINV = 0, 1, 2, 3
 SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
 SGP_TIME_IN_STEP = 256
+SGP_TIME_STEPS = 512
 SGP_OPT_FRAME = 3
 SGP_FRAME_ROTATING, SGP_FRAME_LAB = 0, 1
 
@@ -199,11 +200,13 @@ class Solver:
                 "dM_dt", "dLz_dt")
         return dict(zip(keys, out[:]))
 
-    def time_pass(self, psi, pass_kind, reps, in_step=False):
-        """Average milliseconds of one pass (0 X, 1 Y, 2 Z, 3 inverse Y) over reps
-        launches, timed with HIP events on the library's stream: back to back, or
-        (in_step) inside the pass sequence of a step, one event pair per launch."""
-        pass_kind = int(pass_kind) | (SGP_TIME_IN_STEP if in_step else 0)
+    def time_pass(self, psi, pass_kind, reps, in_step=False, in_steps=False):
+        """Average milliseconds of one pass (0 X, 1 Y, 2 Z, 3 inverse Y), timed with
+        HIP events on the library's stream: reps launches back to back; (in_step)
+        reps rounds of one substep's passes in step order; or (in_steps) every launch
+        of the pass inside reps whole steps of the step schedule, each launch timed
+        by start/end events its dispatch stamps (psi advances reps steps)."""
+        pass_kind = int(pass_kind) | (SGP_TIME_IN_STEP if in_step else 0) | (SGP_TIME_STEPS if in_steps else 0)
         ms = ctypes.c_double()
         _check(lib().sgp_time_pass(self._ctx, self._psi_ptr(psi), int(pass_kind), int(reps), ctypes.byref(ms)),
                self._ctx)
