@@ -393,7 +393,7 @@ hipError_t enqueue_body(sgp_ctx* c, hipStream_t st, void* psi, int nbody) {
 }
 
 void drop_graph(sgp_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
   c->gpsi = nullptr;
   c->gsteps = 0;
@@ -413,10 +413,10 @@ hipError_t get_graph(sgp_ctx* c, void* psi, int gsteps) {
   hipError_t e1 = enqueue_body<T>(c, c->cap, psi, gsteps);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(c->cap, &g);
-  if (e1 != hipSuccess) { if (g) hipGraphDestroy(g); return e1; }
+  if (e1 != hipSuccess) { if (g) (void)hipGraphDestroy(g); return e1; }
   if (e != hipSuccess) return e;
   e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) { c->gexec = nullptr; return e; }
   c->gpsi = psi;
   c->gsteps = gsteps;
@@ -509,15 +509,15 @@ int time_pass_impl(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return hip_fail(c, e, "event create");
   e = hipEventCreate(&e1);
-  if (e != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, e, "event create"); }
+  if (e != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(c, e, "event create"); }
   e = hipEventRecord(e0, c->st);
   for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_timed_pass<T>(c, psi, pass, i == 0);
   if (e == hipSuccess) e = hipEventRecord(e1, c->st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(c, e, "pass timing");
   *avg_ms = (double)ms / reps;
   return SGP_OK;
@@ -593,7 +593,7 @@ int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_m
   hipError_t r = hipEventCreate(&e0);
   if (r != hipSuccess) return hip_fail(c, r, "event create");
   r = hipEventCreate(&e1);
-  if (r != hipSuccess) { hipEventDestroy(e0); return hip_fail(c, r, "event create"); }
+  if (r != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(c, r, "event create"); }
   auto time_steps = [&](double* ms) -> int {
     int rc = step_impl<T>(c, psi, steps);  // untimed: graph capture, warm caches
     if (rc != SGP_OK) return rc;
@@ -634,8 +634,8 @@ int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_m
         }
       }
   for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, best_e[ax]);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   c->t = t_save;
   if (rc != SGP_OK) return rc;
   for (int ax = 0; ax < 3; ++ax) out_e[ax] = ax < c->g.dim ? c->plan_e[ax] : 0;
@@ -1155,7 +1155,7 @@ int sgp_set_option(sgp_ctx* c, int option, long value) {
 void sgp_destroy(sgp_ctx* c) {
   if (!c) return;
   drop_graph(c);
-  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
 
@@ -1218,7 +1218,7 @@ int efail(sgp_ensemble* e, int code, const std::string& msg) {
 enum { ES_XFIRST = 0, ES_XMID = 1, ES_XMERGE = 2, ES_XLAST = 3, ES_LIN0 = 4, ES_LIN1 = 5, ES_N = 6 };
 
 void drop_egraph(sgp_ensemble* e) {
-  if (e->gexec) hipGraphExecDestroy(e->gexec);
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
   e->gexec = nullptr;
   e->gsteps = 0;
 }
@@ -1415,11 +1415,11 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
       hipGraph_t g = nullptr;
       r = hipStreamEndCapture(e->cap, &g);
       if (r1 != hipSuccess || r != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return efail(e, SGP_ERR_HIP, "graph capture");
       }
       r = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (r != hipSuccess) { e->gexec = nullptr; return efail(e, SGP_ERR_HIP, "graph instantiate"); }
       e->gsteps = G;
     }
@@ -1847,10 +1847,10 @@ int sgp_ensemble_set_option(sgp_ensemble* e, int option, long value) {
 void sgp_ensemble_destroy(sgp_ensemble* e) {
   if (!e) return;
   drop_egraph(e);
-  if (e->cap) hipStreamDestroy(e->cap);
-  for (hipStream_t sst : e->side) hipStreamDestroy(sst);
-  for (hipEvent_t ev : e->ev_join) hipEventDestroy(ev);
-  if (e->ev_fork) hipEventDestroy(e->ev_fork);
+  if (e->cap) (void)hipStreamDestroy(e->cap);
+  for (hipStream_t sst : e->side) (void)hipStreamDestroy(sst);
+  for (hipEvent_t ev : e->ev_join) (void)hipEventDestroy(ev);
+  if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
   for (auto* c : e->ctx) sgp_destroy(c);
   delete e;
 }
