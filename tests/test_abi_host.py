@@ -68,6 +68,11 @@ def test_create_validates_arguments():
     assert b"workspace" in L.sgp_last_error(ctx)
     assert L.sgp_set_workspace(ctx, ctypes.c_void_p(256), 1) == -5
     assert L.sgp_set_option(ctx, 99, 0) == -1
+    # pass timing: both timing modes at once, an unknown flag, or a z-pass in 2D are
+    # argument errors, checked before any device work
+    ms = ctypes.c_double()
+    for pk in (256 | 512, 1024, 2 | 512, -1):
+        assert L.sgp_time_pass(ctx, ctypes.c_void_p(1), pk, 4, ctypes.byref(ms)) == -1, pk
     t = ctypes.c_double(-1.0)
     assert L.sgp_set_time(ctx, 0.25) == 0 and L.sgp_get_time(ctx, ctypes.byref(t)) == 0 and t.value == 0.25
     L.sgp_destroy(ctx)
