@@ -55,7 +55,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
+        print(json.dumps({"error": "bench.py runs on one GPU only; sharding across GPUs is a design note, "
                                    "not an implemented path", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
