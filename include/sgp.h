@@ -180,8 +180,9 @@ int sgp_set_time(sgp_ctx* ctx, double t);
  * whole steps of sgp_step's schedule run (launched without the graph; psi
  * advances, the context time is restored) and every launch of the named pass in
  * them is timed by a start/end event pair that its dispatch stamps (pass 0: the
- * X-passes between two linear substeps); the rotating frame only.  Requires a
- * built propagator.  Synchronous. */
+ * X-passes between two linear substeps); the rotating frame only.  In both modes
+ * that time every launch, reps <= 4096.  Requires a built propagator.
+ * Synchronous. */
 enum { SGP_TIME_IN_STEP = 256, SGP_TIME_STEPS = 512 };
 int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_ms);
 

@@ -1042,6 +1042,8 @@ int sgp_time_pass(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms) {
   if ((c->g.dim == 2 && kind > 1) || (pass & ~(SGP_TIME_IN_STEP | SGP_TIME_STEPS | 3)) ||
       ((pass & SGP_TIME_IN_STEP) && (pass & SGP_TIME_STEPS)))
     return fail(c, SGP_ERR_ARG, "no such pass");
+  if ((pass & (SGP_TIME_IN_STEP | SGP_TIME_STEPS)) && reps > 4096)
+    return fail(c, SGP_ERR_ARG, "at most 4096 rounds or steps when every launch is timed");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   if (!c->have_prop) return fail(c, SGP_ERR_STATE, "propagator not built");
   if (pass & SGP_TIME_STEPS) {

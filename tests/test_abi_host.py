@@ -73,6 +73,7 @@ def test_create_validates_arguments():
     ms = ctypes.c_double()
     for pk in (256 | 512, 1024, 2 | 512, -1):
         assert L.sgp_time_pass(ctx, ctypes.c_void_p(1), pk, 4, ctypes.byref(ms)) == -1, pk
+    assert L.sgp_time_pass(ctx, ctypes.c_void_p(1), 512, 5000, ctypes.byref(ms)) == -1  # too many timed steps
     t = ctypes.c_double(-1.0)
     assert L.sgp_set_time(ctx, 0.25) == 0 and L.sgp_get_time(ctx, ctypes.byref(t)) == 0 and t.value == 0.25
     L.sgp_destroy(ctx)
