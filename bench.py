@@ -275,7 +275,18 @@ def main():
         out["cpu_baseline"] = {"value": npts * k / tc, "unit": "gp-steps/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
                                "sample": f"{k} TS{cfg.order} steps of the same workload from the same initial state "
-                                         f"(FP64, own FFT) in {tc:.1f} s"}
+                                         f"(FP64, own FFT) in {tc:.1f} s",
+                               "cpu_model": cpu_model()}
+        # the same oracle on one core, a shorter sample (one step)
+        nthr = oracle.num_threads()
+        oracle.set_threads(1)
+        k1 = 1
+        t0 = time.perf_counter()
+        oracle.evolve(psi0, cfg.L, cfg.params, cfg.order, cfg.tau, k1)
+        t1c = time.perf_counter() - t0
+        oracle.set_threads(nthr)
+        out["cpu_baseline"]["one_core"] = {"value": npts * k1 / t1c, "unit": "gp-steps/s", "cores": 1,
+                                           "sample": f"{k1} TS{cfg.order} steps in {t1c:.1f} s"}
     if a.calib_copy_mb > 0:
         src = torch.empty(a.calib_copy_mb * 2 ** 20, dtype=torch.uint8, device=s.device)
         dst = torch.empty_like(src)
@@ -521,6 +532,17 @@ class UnfusedFP64:
                 psi = self.linear(psi, b[k] * tau)
                 s += b[k] * tau
         return self.nonlinear(psi, a[0] * tau, s)
+
+
+def cpu_model():
+    """The host CPU's model name (first processor of /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def source_hash():

@@ -42,3 +42,4 @@ def test_short_bench_line_has_the_contract_fields():
     assert rf["copy_ceiling"]["GB_per_s"] > 0
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+    assert "cpu_model" in cb and cb["one_core"]["cores"] == 1 and cb["one_core"]["value"] > 0
