@@ -65,7 +65,7 @@ def main():
     if a.workload == "paper-eff":
         return bench_paper_efficiency(a)
     from paper_2603_25282_amd import inputs as I
-    from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, Solver
+    from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, SgpError, Solver
 
     cfg = {"2d": I.C2, "3d": I.C3, "3d-256": I.C3_256}[a.workload]
     if a.workload == "3d-256":
@@ -103,8 +103,12 @@ def main():
     region_ms = ev0.elapsed_time(ev1)
     gps = npts * a.steps / elapsed
     finite = bool(torch.isfinite(torch.view_as_real(psi)).all().item())
-    # the flow conserves mass exactly; what changes is rounding
-    mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
+    # the flow conserves mass exactly; what changes is rounding (None when the
+    # state is no longer finite: the observables report an error)
+    try:
+        mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
+    except SgpError:
+        mass_change = None
 
     # dominant kernel and its average launch duration in the timed region: each
     # pass's share of a step from the start/end events stamped by the dispatches of

@@ -114,7 +114,8 @@ int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
 /* Observables of the state at the current clock (Sec. 2, discrete h^d sums):
  * out[0] mass N, out[1] energy E, out[2] magnetization M, out[3] <Lz>.  Spatial
  * derivatives are spectral; the trap is taken at the rotated point R(Omega t) x.
- * FP64 accumulation.  Synchronous. */
+ * FP64 accumulation.  Returns SGP_ERR_NONFINITE (out still written) when the state
+ * holds a NaN or an infinity.  Synchronous. */
 int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
 
 /* The observables plus the quantities of the dynamical laws of Sec. 2, all FP64:
@@ -131,7 +132,7 @@ int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
  * d<Lz>/dt = (gx^2 - gy^2) out[7] + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] with
  * Q1 = <psi_2, L_- psi_1>, Q2 = <psi_-1, L_- psi_-2>, Q3 = <psi_1, L_- psi_0>,
  * Q4 = <psi_-1, L_+ psi_0>, Q5 = <psi_1, L_+ psi_2>; all frame-invariant.
- * Synchronous. */
+ * SGP_ERR_NONFINITE as sgp_observables.  Synchronous. */
 int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[11]);
 
 /* ---- Differentiation (discrete adjoint of sgp_step) -------------------------

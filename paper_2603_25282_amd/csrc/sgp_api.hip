@@ -726,6 +726,12 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
   out[9] = -2.0 * g * hd * (q1 + q2 + r6h * (q3 - q4)).imag();
   // out[10] = d<Lz>/dt = (gx^2 - gy^2) int x y rho + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] (Lemma 1)
   out[10] = (c->p.gx * c->p.gx - c->p.gy * c->p.gy) * out[7] + 2.0 * g * hd * (q2 - q5 + r6h * (q3 - q4)).imag();
+  // a NaN or infinity anywhere in the state reaches the mass sum (|psi|^2 over all
+  // points) and every other sum
+  for (int axis = 0; axis < c->g.dim; ++axis)
+    for (int q = 0; q < NOBS; ++q)
+      if (!std::isfinite(tot[axis][q]))
+        return fail(c, SGP_ERR_NONFINITE, "the state holds non-finite values (observable sums are not finite)");
   return SGP_OK;
 }
 
@@ -1014,7 +1020,7 @@ int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   double all[11];
   int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
-  if (rc == SGP_OK) std::memcpy(out, all, 4 * sizeof(double));
+  if (rc == SGP_OK || rc == SGP_ERR_NONFINITE) std::memcpy(out, all, 4 * sizeof(double));
   return rc;
 }
 

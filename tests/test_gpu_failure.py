@@ -1,0 +1,68 @@
+"""Failure handling through the C ABI: a NaN or an infinity in the state is
+reported as SGP_ERR_NONFINITE by the observables (the kernels' memory accesses do
+not depend on the data, so such a state is read like any other), and a run cut
+after k steps resumes from its checkpoint (the state and the time) in a fresh
+context bitwise as if it had not been cut."""
+import numpy as np
+import pytest
+
+from paper_2603_25282_amd import inputs as I
+from paper_2603_25282_amd.sgp import SgpError, Solver
+from tests.gpu_util import to_gpu
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = (100.0, -1.0, 5.0, 0.6, 0.7, 1.0, 1.1, 1.0)
+
+
+def _state(shape, L, seed):
+    rng = np.random.default_rng(seed)
+    co = I.mesh(shape, L)
+    g = np.exp(-sum(c * c for c in co) / 2.0)
+    return I.normalise(g[None] * np.exp(1j * rng.uniform(0, 2 * np.pi, (5,) + shape)), shape, L)
+
+
+@pytest.mark.parametrize("dtype", ["complex64", "complex128"])
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_nonfinite_state_is_reported(dtype, bad):
+    shape, L = (64, 64), 8.0
+    print(f"case nonfinite {dtype} {bad}", flush=True)
+    s = Solver(shape, L, PARAMS, dtype=dtype)
+    s.build_propagator(1e-3, 4)
+    psi = to_gpu(s, _state(shape, L, 21))
+    m = s.observables(psi)
+    assert np.all(np.isfinite(m))
+    psi[17, 40, 3] = complex(bad, 0.0)  # one value of one component at one point
+    with pytest.raises(SgpError, match="error -4"):
+        s.observables(psi)
+    with pytest.raises(SgpError, match="error -4"):
+        s.diagnostics(psi)
+
+
+@pytest.mark.parametrize("shape,dtype", [((128, 64), "complex64"), ((32, 32, 32), "complex128")])
+def test_resume_from_checkpoint_is_bitwise(shape, dtype):
+    import torch
+    L, n1, n2 = 8.0, 17, 23
+    print(f"case resume {shape} {dtype}", flush=True)
+    psi0 = _state(shape, L, 22)
+    # the uninterrupted run: the same two calls in one context (a call ends with its
+    # last nonlinear substep unmerged, so the cut sits at the same place)
+    ref = Solver(shape, L, PARAMS, dtype=dtype)
+    ref.build_propagator(1e-3, 4)
+    a = to_gpu(ref, psi0)
+    ref.step(a, n1)
+    ref.step(a, n2)
+    s1 = Solver(shape, L, PARAMS, dtype=dtype)
+    s1.build_propagator(1e-3, 4)
+    b = to_gpu(s1, psi0)
+    s1.step(b, n1)
+    checkpoint, t = b.clone(), s1.time
+    del s1, b
+    s2 = Solver(shape, L, PARAMS, dtype=dtype)  # a fresh context
+    s2.build_propagator(1e-3, 4)
+    s2.time = t
+    c = checkpoint.clone()
+    s2.step(c, n2)
+    torch.cuda.synchronize()
+    assert s2.time == ref.time
+    assert torch.equal(a, c)
