@@ -198,3 +198,23 @@ def test_evolve_keeps_last_segment_and_second_backward(dtype):
     print(f"  state grad {eg:.3e}, params {ed}", flush=True)
     assert eg <= (1e-11 if dtype == "complex128" else 5e-5)
     assert np.all(ed <= (1e-10 if dtype == "complex128" else 2e-4))
+
+
+@pytest.mark.parametrize("shape", [(32, 64), (16, 16, 16)])
+@pytest.mark.parametrize("order", [2, 4])
+def test_dot_product_of_the_linear_step(shape, order):
+    # With c0 = c1 = c2 = 0 the split step is linear in the state (the nonlinear flow
+    # reduces to the trap phase), so the adjoint must satisfy Re<w, S v> = Re<S^H w, v>
+    # to rounding, for any v and w: a check of the adjoint that needs no oracle.
+    L = 6.0
+    params = (0.0, 0.0, 0.0, 0.7, 0.9, 1.0, 1.2, 1.5)
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal((5,) + shape) + 1j * rng.standard_normal((5,) + shape)
+    w = rng.standard_normal((5,) + shape) + 1j * rng.standard_normal((5,) + shape)
+    print(f"case dot product {shape} TS{order}", flush=True)
+    g0, _, Sv = gpu_adjoint(v, w, L, params, order, 4e-3, 9, K=4, dtype="complex128")
+    lhs = np.sum(np.conj(w) * Sv).real
+    rhs = np.sum(np.conj(g0) * v).real
+    scale = np.linalg.norm(w) * np.linalg.norm(Sv)
+    print("  Re<w, Sv>", lhs, "Re<S^H w, v>", rhs, "rel", abs(lhs - rhs) / scale, flush=True)
+    assert abs(lhs - rhs) <= 1e-12 * scale
