@@ -143,7 +143,10 @@ class Solver:
         import numpy as np
         return np.ascontiguousarray(np.moveaxis(np.asarray(psi_clast), -1, 0))
 
-    def __init__(self, shape, L, params, dtype="complex64", device="cuda:0", stream=None):
+    def __init__(self, shape, L, params, dtype="complex64", device="cuda:0", stream=None, poison=False):
+        """poison: fill the workspace with NaN bytes (0xFF) before the library takes
+        it, so that a read of workspace memory the library has not written shows up
+        in the results (a checking mode)."""
         import torch
         self.shape = tuple(int(s) for s in shape)
         dim = len(self.shape)
@@ -168,6 +171,10 @@ class Solver:
         _check(lib().sgp_workspace_size(ctx, ctypes.byref(nb)), ctx)
         # uint8 buffer; torch's caching allocator returns 512-byte aligned blocks
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        if poison:
+            with torch.cuda.device(self.device):
+                self.workspace.fill_(0xFF)
+                torch.cuda.current_stream().synchronize()
         _check(lib().sgp_set_workspace(ctx, ctypes.c_void_p(self.workspace.data_ptr()), nb.value), ctx)
 
     def _psi_ptr(self, psi):
@@ -333,7 +340,7 @@ class Ensemble:
     shapes: list of (N, N); Ls: list of half-widths; params_list: list of
     (c0, c1, c2, Omega, gamma, gx, gy, gz)."""
 
-    def __init__(self, shapes, Ls, params_list, dtype="complex64", device="cuda:0", stream=None):
+    def __init__(self, shapes, Ls, params_list, dtype="complex64", device="cuda:0", stream=None, poison=False):
         import torch
         L = lib()
         vp = ctypes.c_void_p
@@ -379,6 +386,10 @@ class Ensemble:
         nb = ctypes.c_size_t()
         self._chk(L.sgp_ensemble_workspace_size(h, ctypes.byref(nb)))
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        if poison:  # NaN bytes, as for Solver(poison=True)
+            with torch.cuda.device(self.device):
+                self.workspace.fill_(0xFF)
+                torch.cuda.current_stream().synchronize()
         self._chk(L.sgp_ensemble_set_workspace(h, vp(self.workspace.data_ptr()), nb.value))
 
     def _chk(self, rc):

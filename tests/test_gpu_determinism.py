@@ -71,3 +71,39 @@ def test_ensemble_repeats_bitwise():
         torch.cuda.synchronize()
         res.append(psis)
     assert all(torch.equal(x, y) for x, y in zip(res[0], res[1]))
+
+
+@pytest.mark.parametrize("shape,dtype", [((128, 64), "complex64"), ((32, 32, 32), "complex128")])
+def test_poisoned_workspace_changes_nothing(shape, dtype):
+    # A workspace filled with NaN bytes before the library takes it: every value the
+    # kernels read from it (tables, twiddles, clock, partial sums) must have been
+    # written first, so the results are bitwise those of a workspace as allocated.
+    import torch
+    print(f"case poison {shape} {dtype}", flush=True)
+    psi0 = _state(shape, 8.0, 43)
+    out = []
+    for poison in (False, True):
+        s = Solver(shape, 8.0, PARAMS, dtype=dtype, poison=poison)
+        s.build_propagator(1e-3, 4)
+        psi = to_gpu(s, psi0)
+        s.step(psi, 40)
+        out.append((psi, s.observables(psi), np.array(list(s.diagnostics(psi).values()))))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_poisoned_ensemble_workspace_changes_nothing():
+    import torch
+    insts = I.ensemble_instances(n128=2, n256=1, n384=1)
+    res = []
+    for poison in (False, True):
+        ens = Ensemble([c.shape for c in insts], [c.L for c in insts], [c.params for c in insts], dtype="complex64",
+                       poison=poison)
+        ens.build_propagator(insts[0].tau, insts[0].order)
+        psis = [torch.from_numpy(Solver.to_device_layout(I.initial_state(c))).to(torch.complex64).cuda().contiguous()
+                for c in insts]
+        ens.step(psis, 20)
+        torch.cuda.synchronize()
+        res.append(psis)
+    assert all(torch.equal(x, y) for x, y in zip(res[0], res[1]))
