@@ -157,6 +157,9 @@ class Solver:
             g.n[i] = self.shape[::-1][i] if i < dim else 1
             g.L[i] = float(Ls[i]) if i < dim else 0.0
         p = _Params(*[float(x) for x in params])
+        self.L = tuple(float(x) for x in Ls)
+        self.params = tuple(float(x) for x in params)
+        self.tau, self.scheme = None, None
         self.torch_dtype = {"complex64": torch.complex64, "complex128": torch.complex128}[str(dtype).replace(
             "torch.", "")]
         code = SGP_C64 if self.torch_dtype == torch.complex64 else SGP_C128
@@ -187,6 +190,7 @@ class Solver:
 
     def build_propagator(self, tau, scheme):
         _check(lib().sgp_build_propagator(self._ctx, float(tau), int(scheme)), self._ctx)
+        self.tau, self.scheme = float(tau), int(scheme)
 
     def step(self, psi, nsteps):
         _check(lib().sgp_step(self._ctx, self._psi_ptr(psi), int(nsteps)), self._ctx)

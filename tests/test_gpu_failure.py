@@ -66,3 +66,29 @@ def test_resume_from_checkpoint_is_bitwise(shape, dtype):
     torch.cuda.synchronize()
     assert s2.time == ref.time
     assert torch.equal(a, c)
+
+
+def test_checkpoint_file_roundtrip(tmp_path):
+    # kill after k steps, write the checkpoint file, resume from it in a fresh
+    # context: bitwise the run that went on in place (plans and clock restored)
+    import torch
+    from paper_2603_25282_amd import checkpoint
+    shape, L, n1, n2 = (64, 128), 8.0, 17, 23
+    print(f"case checkpoint file {shape}", flush=True)
+    s = Solver(shape, L, PARAMS, dtype="complex64")
+    s.set_plan([4, 4])  # not the default plans, so that they must come back from the file
+    s.build_propagator(1e-3, 4)
+    psi = to_gpu(s, _state(shape, L, 23))
+    s.step(psi, n1)
+    path = str(tmp_path / "run.npz")
+    checkpoint.save(path, s, psi)
+    s.step(psi, n2)  # the run that is not cut
+    torch.cuda.synchronize()
+    s2, psi2 = checkpoint.load(path)
+    assert s2.get_plan() == [4, 4] and s2.shape == shape and s2.params == s.params
+    s2.step(psi2, n2)
+    torch.cuda.synchronize()
+    assert s2.time == s.time
+    assert torch.equal(psi, psi2)
+    with np.load(path, allow_pickle=False) as f:  # plain arrays only
+        assert set(f.files) >= {"state", "time", "shape", "L", "params", "tau", "scheme", "plan", "dtype"}
