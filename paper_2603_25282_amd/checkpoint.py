@@ -44,3 +44,39 @@ def load(path, device="cuda:0", stream=None):
     if psi.dtype != s.torch_dtype or tuple(psi.shape) != s.shape + (5,):
         raise ValueError("checkpoint state does not match its configuration")
     return s, psi
+
+
+class WatchdogError(RuntimeError):
+    pass
+
+
+def run_checked(solver, psi, nsteps, every, path=None, mass_tol=None):
+    """Advance psi by nsteps in calls of `every` steps; after each call check the
+    state (sgp_observables reports a NaN or an infinity anywhere in it as
+    SGP_ERR_NONFINITE) and, with mass_tol, the relative change of the mass since
+    the start; with path, write a checkpoint file after each call.  Raises
+    WatchdogError naming the step where a check failed (the last checkpoint
+    written, if any, is the state `every` steps earlier).  Each call ends with
+    its last nonlinear substep unmerged, so the result depends on `every` at the
+    level of rounding."""
+    from .sgp import SgpError
+    if every < 1:
+        raise ValueError("every must be >= 1")
+    try:
+        m0 = float(solver.observables(psi)[0])
+    except SgpError as e:
+        raise WatchdogError(f"step 0: {e}") from e
+    done = 0
+    while done < nsteps:
+        k = min(every, nsteps - done)
+        solver.step(psi, k)
+        done += k
+        try:
+            m = float(solver.observables(psi)[0])
+        except SgpError as e:
+            raise WatchdogError(f"step {done}: {e}") from e
+        if mass_tol is not None and abs(m / m0 - 1.0) > mass_tol:
+            raise WatchdogError(f"step {done}: relative mass change {m / m0 - 1.0:.3e} exceeds {mass_tol:.3e}")
+        if path is not None:
+            save(path, solver, psi)
+    return psi

@@ -92,3 +92,24 @@ def test_checkpoint_file_roundtrip(tmp_path):
     assert torch.equal(psi, psi2)
     with np.load(path, allow_pickle=False) as f:  # plain arrays only
         assert set(f.files) >= {"state", "time", "shape", "L", "params", "tau", "scheme", "plan", "dtype"}
+
+
+def test_watchdog_runs_and_stops(tmp_path):
+    import torch
+    from paper_2603_25282_amd import checkpoint
+    shape, L = (64, 64), 8.0
+    print("case watchdog", flush=True)
+    s = Solver(shape, L, PARAMS, dtype="complex128")
+    s.build_propagator(1e-3, 4)
+    psi = to_gpu(s, _state(shape, L, 24))
+    path = str(tmp_path / "w.npz")
+    checkpoint.run_checked(s, psi, 25, every=10, path=path, mass_tol=1e-10)
+    assert abs(s.time - 0.025) < 1e-15
+    s2, psi2 = checkpoint.load(path)  # the last checkpoint is the final state
+    assert torch.equal(psi, psi2) and s2.time == s.time
+    # a mass tolerance below the rounding of the steps stops the run after the first call
+    with pytest.raises(checkpoint.WatchdogError, match="step 10: relative mass change"):
+        checkpoint.run_checked(s, psi.clone(), 20, every=10, mass_tol=1e-30)
+    psi[5, 7, 1] = complex(float("nan"), 0.0)  # a corrupted state stops the run at once
+    with pytest.raises(checkpoint.WatchdogError, match="step 0: sgp error -4"):
+        checkpoint.run_checked(s, psi, 20, every=10)
