@@ -31,11 +31,27 @@ def _solver(shape, L, params, trap, dtype, tau, order, plan=None, psi=None):
     return s
 
 
+def check_solver(s, psi0, params, shape, L, trap, tau, order):
+    """A prebuilt Solver must be the one evolve() would build: same grid, physics
+    (params = (gamma, Omega, c0, c1, c2) and trap), element type, tau and scheme."""
+    g, Om, c0, c1, c2 = [float(x) for x in params]
+    want = (c0, c1, c2, Om, g, float(trap[0]), float(trap[1]), float(trap[2]))
+    Ls = tuple(float(x) for x in (L if hasattr(L, "__len__") else [L] * len(shape)))
+    if (tuple(s.shape) != tuple(shape) or s.params != want or s.L != Ls or s.torch_dtype != psi0.dtype
+            or s.tau != float(tau) or s.scheme != int(order) or s.frame != "rotating"):
+        raise ValueError("the prebuilt solver does not match the evolution's grid, parameters, dtype, tau or scheme")
+
+
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, psi0, params, shape, L, trap, tau, nsteps, order, K, t0, plan):
+    def forward(ctx, psi0, params, shape, L, trap, tau, nsteps, order, K, t0, plan, solver):
         dtype = "complex64" if psi0.dtype == torch.complex64 else "complex128"
-        s = _solver(shape, L, params.detach().cpu().tolist(), trap, dtype, tau, order, plan, psi0.detach())
+        pars = params.detach().cpu().tolist()
+        if solver is not None:
+            check_solver(solver, psi0, pars, shape, L, trap, tau, order)
+            s = solver
+        else:
+            s = _solver(shape, L, pars, trap, dtype, tau, order, plan, psi0.detach())
         psi = psi0.detach().clone().contiguous()
         keep = any(ctx.needs_input_grad[:2])
         ckpts, store = [], None
@@ -51,6 +67,7 @@ class _Evolve(torch.autograd.Function):
                 s.step(psi, ns)
         ctx.s, ctx.ckpts, ctx.store = s, ckpts, store
         ctx.meta = (tau, nsteps, K, t0)
+        ctx.pmeta = (params.dtype, params.device)
         return psi
 
     @staticmethod
@@ -75,18 +92,22 @@ class _Evolve(torch.autograd.Function):
                 s.step_store(psi, ns, store)
             s.time = t0 + n0 * tau
             s.adjoint_segment(lam, ns, store)
-        dpar = torch.tensor(s.adjoint_gradients(reset=True), dtype=torch.float64)
-        return lam, dpar, None, None, None, None, None, None, None, None, None
+        pdtype, pdev = ctx.pmeta
+        dpar = torch.tensor(s.adjoint_gradients(reset=True), dtype=pdtype, device=pdev)
+        return lam, dpar, None, None, None, None, None, None, None, None, None, None
 
 
-def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0, plan=None):
+def evolve(psi0, params, shape, L, trap, tau, nsteps, order=4, K=50, t0=0.0, plan=None, solver=None):
     """plan: None (default register plans), a list of plan widths per axis (x, y (, z)),
-    or "auto" (autotuned, through the JSON plan cache)."""
+    or "auto" (autotuned, through the JSON plan cache).  solver: a prebuilt Solver
+    (propagator built for tau and order; its plans are used) so that repeated calls
+    set nothing up; it must match the grid, parameters, trap and element type.  The
+    parameter gradient comes back with the dtype and device of params."""
     if not isinstance(params, torch.Tensor):
         params = torch.tensor(params, dtype=torch.float64)
     plan = plan if plan is None or plan == "auto" else tuple(int(e) for e in plan)
     return _Evolve.apply(psi0, params, tuple(shape), L, tuple(trap), float(tau), int(nsteps), int(order), int(K),
-                         float(t0), plan)
+                         float(t0), plan, solver)
 
 
 class _ToLab(torch.autograd.Function):
@@ -153,6 +174,7 @@ class _EnsembleEvolve(torch.autograd.Function):
             else:
                 ens.step(states, ns)
         ctx.ens, ctx.ckpts, ctx.store, ctx.meta = ens, ckpts, store, meta
+        ctx.pmeta = (params.dtype, params.device)
         return tuple(states)
 
     @staticmethod
@@ -177,7 +199,7 @@ class _EnsembleEvolve(torch.autograd.Function):
                 ens.step_store(states, ns, store)
             ens.time = t0 + n0 * tau
             ens.adjoint_segment(lams, ns, store)
-        dpar = torch.tensor(ens.adjoint_gradients(reset=True), dtype=torch.float64)
+        dpar = torch.tensor(ens.adjoint_gradients(reset=True), dtype=ctx.pmeta[0], device=ctx.pmeta[1])
         return (None, None, dpar) + tuple(lams)
 
 

@@ -1,43 +1,62 @@
 """Checkpoint files of a run: the state together with everything that determines
 its continuation -- the clock t of the rotating frame (the trap angle Omega t and
 the first nonlinear substep of the next call depend on it), grid, half-widths,
-physics parameters, element type, time step, composition and register plans.
+physics parameters, element type, time step, composition, register plans and the
+frame option (rotating-frame Phi, or the lab-frame state of Algorithm 1).
 
 A call of sgp_step ends with its last nonlinear substep unmerged, so a run
 resumed from a checkpoint written between two calls continues bitwise as the
 same calls in one context would.  Files are numpy .npz archives of plain arrays
 (no pickled objects); load() reads them with allow_pickle=False."""
+import os
+
 import numpy as np
 
 from .sgp import Solver
 
-FORMAT = 1
+# 2: the frame option (rotating-frame Phi or the literal lab-frame Algorithm 1) is stored
+FORMAT = 2
 
 
 def save(path, solver, psi):
     """Write psi (the solver's state tensor, library layout) and the solver's
-    configuration to `path` (.npz).  The propagator must have been built."""
+    configuration to `path` exactly (no suffix is added).  The propagator must have
+    been built.  The state is copied only after the solver's stream has finished
+    every queued step, and the file is written to a temporary name and then renamed,
+    so that a process killed while writing leaves the previous checkpoint whole."""
+    import torch
     if solver.tau is None:
         raise ValueError("build the propagator before saving a checkpoint")
+    with torch.cuda.device(solver.device):
+        if solver.stream is not None:
+            solver.stream.synchronize()
+        torch.cuda.current_stream().synchronize()
     state = psi.detach().cpu().numpy()
-    np.savez(path, format=np.int64(FORMAT), state=state, time=np.float64(solver.time),
-             shape=np.asarray(solver.shape, dtype=np.int64), L=np.asarray(solver.L, dtype=np.float64),
-             params=np.asarray(solver.params, dtype=np.float64), tau=np.float64(solver.tau),
-             scheme=np.int64(solver.scheme), plan=np.asarray(solver.get_plan(), dtype=np.int64),
-             dtype=np.bytes_(str(solver.torch_dtype).replace("torch.", "")))
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, format=np.int64(FORMAT), state=state, time=np.float64(solver.time),
+                 shape=np.asarray(solver.shape, dtype=np.int64), L=np.asarray(solver.L, dtype=np.float64),
+                 params=np.asarray(solver.params, dtype=np.float64), tau=np.float64(solver.tau),
+                 scheme=np.int64(solver.scheme), plan=np.asarray(solver.get_plan(), dtype=np.int64),
+                 frame=np.bytes_(solver.frame),
+                 dtype=np.bytes_(str(solver.torch_dtype).replace("torch.", "")))
+        f.flush()
+        os.fsync(f.fileno())
+    os.replace(tmp, path)
 
 
 def load(path, device="cuda:0", stream=None):
-    """Read a checkpoint; returns (solver, psi) with the propagator built, the plans
-    and the clock restored, and psi on `device` in the library layout."""
+    """Read a checkpoint; returns (solver, psi) with the propagator built, the plans,
+    the frame and the clock restored, and psi on `device` in the library layout."""
     import torch
-    with np.load(path, allow_pickle=False) as f:
+    with open(path, "rb") as fh, np.load(fh, allow_pickle=False) as f:
         if int(f["format"]) != FORMAT:
             raise ValueError(f"unknown checkpoint format {int(f['format'])}")
         dtype = f["dtype"].item().decode()
         s = Solver(tuple(int(x) for x in f["shape"]), tuple(float(x) for x in f["L"]),
                    tuple(float(x) for x in f["params"]), dtype=dtype, device=device, stream=stream)
         s.set_plan([int(x) for x in f["plan"]])
+        s.set_frame(f["frame"].item().decode())
         s.build_propagator(float(f["tau"]), int(f["scheme"]))
         s.time = float(f["time"])
         psi = torch.from_numpy(np.array(f["state"])).to(s.device).contiguous()

@@ -160,6 +160,7 @@ class Solver:
         self.L = tuple(float(x) for x in Ls)
         self.params = tuple(float(x) for x in params)
         self.tau, self.scheme = None, None
+        self.frame = "rotating"
         self.torch_dtype = {"complex64": torch.complex64, "complex128": torch.complex128}[str(dtype).replace(
             "torch.", "")]
         code = SGP_C64 if self.torch_dtype == torch.complex64 else SGP_C128
@@ -311,6 +312,7 @@ class Solver:
         """'rotating' (default) or 'lab' (Algorithm 1 literally on the lab-frame state)."""
         v = {"rotating": SGP_FRAME_ROTATING, "lab": SGP_FRAME_LAB}[frame]
         _check(lib().sgp_set_option(self._ctx, SGP_OPT_FRAME, v), self._ctx)
+        self.frame = frame
 
     def set_graph(self, on):
         _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)
@@ -404,11 +406,7 @@ class Ensemble:
         self._chk(lib().sgp_ensemble_build_propagator(self._h, float(tau), int(scheme)))
 
     def step(self, psis, nsteps):
-        for p, sh in zip(psis, self.shapes):
-            if p.dtype != self.torch_dtype or tuple(p.shape) != sh + (5,) or not p.is_contiguous():
-                raise SgpError("ensemble states must be contiguous (N, N, 5) tensors of the ensemble dtype")
-        arr = (ctypes.c_void_p * len(psis))(*[p.data_ptr() for p in psis])
-        self._chk(lib().sgp_ensemble_step(self._h, arr, int(nsteps)))
+        self._chk(lib().sgp_ensemble_step(self._h, self._ptrs(psis), int(nsteps)))
 
     def set_option(self, option, value):
         self._chk(lib().sgp_ensemble_set_option(self._h, int(option), int(value)))
@@ -424,9 +422,16 @@ class Ensemble:
         self._chk(lib().sgp_ensemble_set_time(self._h, float(t)))
 
     def _ptrs(self, psis):
+        """Pointer array for the C ABI, which reads one pointer per instance: refuse a
+        list of the wrong length before any library call."""
+        psis = list(psis)
+        if len(psis) != len(self.shapes):
+            raise SgpError(f"ensemble of {len(self.shapes)} instances given {len(psis)} states")
         for p, sh in zip(psis, self.shapes):
             if p.dtype != self.torch_dtype or tuple(p.shape) != sh + (5,) or not p.is_contiguous():
                 raise SgpError("ensemble states must be contiguous (N, N, 5) tensors of the ensemble dtype")
+            if p.device != self.device:
+                raise SgpError("ensemble states must be on the ensemble's device")
         return (ctypes.c_void_p * len(psis))(*[p.data_ptr() for p in psis])
 
     def store_size(self, nsteps):
@@ -463,8 +468,9 @@ class Ensemble:
 
     def autotune(self, psis, steps=10):
         """sgp_ensemble_autotune on scratch copies of psis; returns (plans(), ms per step)."""
+        self._ptrs(psis)
         scratch = [p.clone() for p in psis]
-        arr = (ctypes.c_void_p * len(scratch))(*[p.data_ptr() for p in scratch])
+        arr = self._ptrs(scratch)
         ms = ctypes.c_double()
         self._chk(lib().sgp_ensemble_autotune(self._h, arr, int(steps), ctypes.byref(ms)))
         del scratch

@@ -178,3 +178,23 @@ def test_ensemble_adjoint_entry_points_validate_without_device():
     t = ctypes.c_double()
     assert L.sgp_ensemble_get_time(h, ctypes.byref(t)) == 0 and t.value == 0.25
     L.sgp_ensemble_destroy(h)
+
+
+def test_ensemble_binding_refuses_a_state_list_of_the_wrong_length():
+    # the C ABI reads one state pointer per instance: the binding must refuse a list
+    # of another length before any library call (here there is no library handle at
+    # all, so reaching the library would fail differently)
+    import torch
+    e = object.__new__(sgp.Ensemble)
+    e.shapes = [(64, 64), (128, 128)]
+    e.torch_dtype = torch.complex64
+    e.device = torch.device("cpu")
+    e._h = None
+    one = [torch.zeros((64, 64, 5), dtype=torch.complex64)]
+    three = one + [torch.zeros((128, 128, 5), dtype=torch.complex64), torch.zeros((8, 8, 5), dtype=torch.complex64)]
+    for psis in (one, three):
+        for call in (lambda p: e.step(p, 1), lambda p: e.step_store(p, 1, torch.zeros(8, dtype=torch.uint8)),
+                     lambda p: e.adjoint_segment(p, 1, torch.zeros(8, dtype=torch.uint8)),
+                     lambda p: e.autotune(p)):
+            with pytest.raises(sgp.SgpError, match="instances given"):
+                call(psis)

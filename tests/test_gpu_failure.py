@@ -3,6 +3,8 @@ reported as SGP_ERR_NONFINITE by the observables (the kernels' memory accesses d
 not depend on the data, so such a state is read like any other), and a run cut
 after k steps resumes from its checkpoint (the state and the time) in a fresh
 context bitwise as if it had not been cut."""
+import os
+
 import numpy as np
 import pytest
 
@@ -91,7 +93,42 @@ def test_checkpoint_file_roundtrip(tmp_path):
     assert s2.time == s.time
     assert torch.equal(psi, psi2)
     with np.load(path, allow_pickle=False) as f:  # plain arrays only
-        assert set(f.files) >= {"state", "time", "shape", "L", "params", "tau", "scheme", "plan", "dtype"}
+        assert set(f.files) >= {"state", "time", "shape", "L", "params", "tau", "scheme", "plan", "dtype",
+                                "frame"}
+
+
+def test_checkpoint_lab_frame_side_stream(tmp_path):
+    # a lab-frame run (Algorithm 1 literally) on a side stream: the file written right
+    # after the steps were queued holds the finished state and the frame, so the
+    # resumed run continues in the lab frame bitwise; the path has no .npz suffix
+    import torch
+    from paper_2603_25282_amd import checkpoint
+    shape, L, n1, n2 = (64, 64), 8.0, 9, 7
+    print(f"case checkpoint lab frame side stream {shape}", flush=True)
+    side = torch.cuda.Stream()
+    s = Solver(shape, L, PARAMS, dtype="complex128", stream=side)
+    s.set_frame("lab")
+    s.build_propagator(1e-3, 2)
+    psi = to_gpu(s, _state(shape, L, 25))
+    torch.cuda.synchronize()
+    s.step(psi, n1)  # queued on the side stream; save() must wait for it
+    path = str(tmp_path / "lab_run")
+    checkpoint.save(path, s, psi)
+    assert os.path.exists(path) and not os.path.exists(path + ".npz")
+    s.step(psi, n2)
+    side.synchronize()
+    s2, psi2 = checkpoint.load(path)
+    assert s2.frame == "lab"
+    s2.step(psi2, n2)
+    torch.cuda.synchronize()
+    assert s2.time == s.time
+    assert torch.equal(psi, psi2)
+    # the same data resumed in the rotating frame would differ
+    s3, psi3 = checkpoint.load(path)
+    s3.set_frame("rotating")
+    s3.step(psi3, n2)
+    torch.cuda.synchronize()
+    assert not torch.equal(psi, psi3)
 
 
 def test_watchdog_runs_and_stops(tmp_path):
