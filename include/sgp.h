@@ -114,9 +114,23 @@ int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
 /* Observables of the state at the current clock (Sec. 2, discrete h^d sums):
  * out[0] mass N, out[1] energy E, out[2] magnetization M, out[3] <Lz>.  Spatial
  * derivatives are spectral; the trap is taken at the rotated point R(Omega t) x.
- * FP64 accumulation.  Returns SGP_ERR_NONFINITE (out still written) when the state
- * holds a NaN or an infinity.  Synchronous. */
+ * FP64 accumulation: per-block partial sums, added on the device in a fixed order
+ * (bitwise reproducible); only the totals are copied to the host.  Returns
+ * SGP_ERR_NONFINITE (out still written) when the state holds a NaN or an infinity.
+ * Synchronous. */
 int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
+
+/* The inner product <u, J_z v>_h = h^d sum_x sum_l conj(u_l(x)) (J_z v)_l(x) of two
+ * states (layout above, the context's element type) with the generator of the
+ * rotation about z, J_z = L_z + F_z: L_z = -i (x d_y - y d_x) (Sec. 2, the angular
+ * momentum of <Lz>), spectral derivatives, and F_z = diag(2, 1, 0, -1, -2) (Sec. 1).
+ * The rotation mapping of Sec. 3.1 turns a state by the angle Omega t, so
+ * d/dOmega of a function of the mapped state is a real part of such a product
+ * (the lab-frame output's Omega gradient).  out[0] = real part, out[1] = imaginary
+ * part.  FP64 accumulation, block partials summed on the device in a fixed order.
+ * u_dev and v_dev are read only (they may alias).  Returns SGP_ERR_NONFINITE when
+ * the result is not finite.  Synchronous. */
+int sgp_jz_inner(sgp_ctx* ctx, const void* u_dev, const void* v_dev, double out[2]);
 
 /* The observables plus the quantities of the dynamical laws of Sec. 2, all FP64:
  * out[0..3] as sgp_observables; out[4], out[5], out[6] = the widths delta_x,

@@ -118,6 +118,7 @@ class _ToLab(torch.autograd.Function):
         lab = phi.detach().clone().contiguous()
         s.rotation_map(lab, t, -1)
         ctx.s, ctx.t, ctx.hd = s, t, math.prod(2.0 * L / n for n in shape)
+        ctx.Om_dtype, ctx.Om_device = Omega.dtype, Omega.device
         ctx.save_for_backward(lab)
         return lab
 
@@ -131,13 +132,10 @@ class _ToLab(torch.autograd.Function):
         dOm = None
         if ctx.needs_input_grad[1]:
             # the map rotates by the angle Omega t: d lab / d Omega = -i t J_z lab with
-            # J_z = L_z + F_z, so dJ/dOmega = -t Im<g, J_z lab>; Im<g, J_z lab> = Re<i g, J_z lab>
-            # by polarization from <u, J_z u> = (<Lz> + M)(u) / h^d (the observables)
-            u = 1j * g
-            op = s.observables((u + lab).contiguous())
-            om = s.observables((u - lab).contiguous())
-            im = ((op[3] + op[2]) - (om[3] + om[2])) / (4.0 * ctx.hd)
-            dOm = torch.tensor(-t * im, dtype=torch.float64)
+            # J_z = L_z + F_z, so dJ/dOmega = Re<g, -i t J_z lab> / h^d = -t Im<g, J_z lab>_h / h^d
+            # (<,>_h carries h^d; the gradient convention does not)
+            ip = s.jz_inner(g, lab)
+            dOm = torch.tensor(-t * ip.imag / ctx.hd, dtype=ctx.Om_dtype, device=ctx.Om_device)
         return gin, dOm, None, None, None
 
 

@@ -87,6 +87,7 @@ struct sgp_ctx {
   size_t off_kin[4][3];
   size_t off_clock;
   size_t off_part;
+  size_t off_red;        // on-device sums of the observables' block partials (3 x NOBS)
   size_t off_gacc;
   long ngacc = 0;  // blocks with a gradient slot
 
@@ -103,11 +104,13 @@ struct sgp_ctx {
   double t = 0.0;
   std::string err;
 
-  // replay of the periodic part of sgp_step: `gsteps` whole steps captured once
+  // replay of the periodic part of sgp_step: graphs of 2^k whole steps
+  // (k = 0..kGraphLevels-1), all captured together for the state pointer gpsi, so
+  // that any number of body steps replays from graphs (its binary digits)
+  static constexpr int kGraphLevels = 6;
   hipStream_t cap = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec[kGraphLevels] = {};
   void* gpsi = nullptr;
-  int gsteps = 0;
   bool use_graph = true;
 
   // measurement hook (sgp_time_pass with SGP_TIME_STEPS): while it is set, every
@@ -393,33 +396,43 @@ hipError_t enqueue_body(sgp_ctx* c, hipStream_t st, void* psi, int nbody) {
 }
 
 void drop_graph(sgp_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  c->gexec = nullptr;
+  for (auto& g : c->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   c->gpsi = nullptr;
-  c->gsteps = 0;
 }
 
+// Capture the body graphs of 1, 2, 4, ..., 2^(kGraphLevels-1) steps for state psi
+// (all at once, so that a later call with another step count captures nothing).
 template <typename T>
-hipError_t get_graph(sgp_ctx* c, void* psi, int gsteps) {
-  if (c->gexec && c->gpsi == psi && c->gsteps == gsteps) return hipSuccess;
+hipError_t get_graphs(sgp_ctx* c, void* psi) {
+  if (c->gpsi == psi && c->gexec[0]) return hipSuccess;
   drop_graph(c);
   hipError_t e;
   if (!c->cap) {
     e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
   }
-  e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  hipError_t e1 = enqueue_body<T>(c, c->cap, psi, gsteps);
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(c->cap, &g);
-  if (e1 != hipSuccess) { if (g) (void)hipGraphDestroy(g); return e1; }
-  if (e != hipSuccess) return e;
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) { c->gexec = nullptr; return e; }
+  for (int k = 0; k < sgp_ctx::kGraphLevels; ++k) {
+    e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { drop_graph(c); return e; }
+    hipError_t e1 = enqueue_body<T>(c, c->cap, psi, 1 << k);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap, &g);
+    if (e1 != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      drop_graph(c);
+      return e1 != hipSuccess ? e1 : e;
+    }
+    e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->gexec[k] = nullptr; drop_graph(c); return e; }
+    // stage the executable graph on the device now, not at its first replay
+    e = hipGraphUpload(c->gexec[k], c->st);
+    if (e != hipSuccess) { drop_graph(c); return e; }
+  }
   c->gpsi = psi;
-  c->gsteps = gsteps;
   return hipSuccess;
 }
 
@@ -431,15 +444,22 @@ int step_impl(sgp_ctx* c, void* psi, long nsteps) {
   hipError_t e = run_xpass<T>(c, c->st, X_FIRST, psi, nl[0], CLOCK_ARG, c->t);
   if (e != hipSuccess) return hip_fail(c, e, "X-pass launch");
   long nbody = nsteps - 1;
-  const int G = 32;
-  if (c->use_graph && nbody >= G) {
-    e = get_graph<T>(c, psi, G);
+  if (c->use_graph && nbody > 0) {
+    // the body steps replayed from graphs: nbody / 2^(L-1) replays of the largest,
+    // then one replay per binary digit of the remainder (largest first)
+    e = get_graphs<T>(c, psi);
     if (e != hipSuccess) return hip_fail(c, e, "graph capture");
-    for (long i = 0; i < nbody / G; ++i) {
-      e = hipGraphLaunch(c->gexec, c->st);
+    const int top = sgp_ctx::kGraphLevels - 1;
+    for (long i = 0; i < (nbody >> top); ++i) {
+      e = hipGraphLaunch(c->gexec[top], c->st);
       if (e != hipSuccess) return hip_fail(c, e, "graph launch");
     }
-    nbody %= G;
+    for (int k = top - 1; k >= 0; --k)
+      if ((nbody >> k) & 1) {
+        e = hipGraphLaunch(c->gexec[k], c->st);
+        if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+      }
+    nbody = 0;
   }
   if (nbody > 0) {
     e = enqueue_body<T>(c, c->st, psi, (int)nbody);
@@ -665,6 +685,7 @@ long pass_nblocks(const sgp_ctx* c, int axis, int e) {
 template <typename T>
 int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
   double* part = (double*)c->at(c->off_part);
+  double* red = (double*)c->at(c->off_red);
   double tot[3][NOBS];
   for (int axis = 0; axis < c->g.dim; ++axis) {
     PassArgs a = base_args(c);
@@ -679,16 +700,15 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
     const int kind = axis == 0 ? OBS_X : (axis == 1 ? OBS_Y : OBS_Z);
     hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], c->elems(axis), part, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "observables launch");
-    const long nb = obs_nblocks(c, axis, c->elems(axis));
-    std::vector<double> host((size_t)nb * NOBS);
-    e = hipMemcpyAsync(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->st);
+    // block partials summed on the device in a fixed order (the next axis's launch
+    // reuses the partials after this sum on the same stream)
+    e = launch_sum_partials(part, obs_nblocks(c, axis, c->elems(axis)), NOBS, red + axis * NOBS, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "observables reduction");
+  }
+  {
+    hipError_t e = hipMemcpyAsync(&tot[0][0], red, sizeof(double) * NOBS * c->g.dim, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) return hip_fail(c, e, "observables readback");
-    for (int q = 0; q < NOBS; ++q) {
-      double s = 0.0;
-      for (long b = 0; b < nb; ++b) s += host[(size_t)b * NOBS + q];
-      tot[axis][q] = s;
-    }
   }
   double hd = 1.0;
   for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
@@ -732,6 +752,41 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
     for (int q = 0; q < NOBS; ++q)
       if (!std::isfinite(tot[axis][q]))
         return fail(c, SGP_ERR_NONFINITE, "the state holds non-finite values (observable sums are not finite)");
+  return SGP_OK;
+}
+
+// <u, J_z v>_h = h^d sum conj(u) (L_z + F_z) v, L_z = -i (x d_y - y d_x) with
+// spectral derivatives: one x-line pass (i y d_x v + F_z v) and one y-column pass
+// (-i x d_y v), block partials summed on the device.
+template <typename T>
+int jz_inner_impl(sgp_ctx* c, const void* u, const void* v, double out[2]) {
+  double* part = (double*)c->at(c->off_part);
+  double* red = (double*)c->at(c->off_red);
+  for (int axis = 0; axis < 2; ++axis) {
+    PassArgs a = base_args(c);
+    if (axis == 0) {
+      a.tw_fwd = c->at(c->off_tw[0][0]);
+      a.tw_inv = c->at(c->off_tw[0][1]);
+      a.nu_scale_l = kPi / c->g.L[0];
+    } else {
+      column_geometry(c, 1, a);
+    }
+    a.fwd = u;
+    hipError_t e = launch_obs<T>(axis == 0 ? OBS_JX : OBS_JY, v, a, c->g.n[axis], c->elems(axis), part, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "J_z inner product launch");
+    e = launch_sum_partials(part, obs_nblocks(c, axis, c->elems(axis)), NOBS, red + axis * NOBS, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "J_z inner product reduction");
+  }
+  double tot[2][NOBS];
+  hipError_t e = hipMemcpyAsync(&tot[0][0], red, sizeof(double) * 2 * NOBS, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return hip_fail(c, e, "J_z inner product readback");
+  double hd = 1.0;
+  for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
+  out[0] = hd * (tot[0][0] + tot[1][0]);
+  out[1] = hd * (tot[0][1] + tot[1][1]);
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+    return fail(c, SGP_ERR_NONFINITE, "non-finite values in the states of the J_z inner product");
   return SGP_OK;
 }
 
@@ -933,6 +988,8 @@ int sgp_create(const sgp_grid* grid, const sgp_params* params, int dtype, void* 
     for (int e : plan_widths(c->g.n[axis], (int)c->esize))
       maxb = std::max(maxb, std::max(obs_nblocks(c, axis, e), pass_nblocks(c, axis, e)));
   off += align256(sizeof(double) * NOBS * maxb);
+  c->off_red = off;
+  off += align256(sizeof(double) * 3 * NOBS);
   const long gb = maxb;
   c->ngacc = gb;
   c->off_gacc = off;
@@ -1022,6 +1079,12 @@ int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
   if (rc == SGP_OK || rc == SGP_ERR_NONFINITE) std::memcpy(out, all, 4 * sizeof(double));
   return rc;
+}
+
+int sgp_jz_inner(sgp_ctx* c, const void* u, const void* v, double out[2]) {
+  if (!c || !u || !v || !out) return fail(c, SGP_ERR_ARG, "null argument");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  return c->dtype == SGP_C64 ? jz_inner_impl<float>(c, u, v, out) : jz_inner_impl<double>(c, u, v, out);
 }
 
 int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[11]) {

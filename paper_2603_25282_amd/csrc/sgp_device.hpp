@@ -501,21 +501,28 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[NC][E], cx<T>* lx, int t, co
 // the coefficient and the near-identity maps of small time steps repeat no O(1)
 // rounding error from step to step.
 // ---------------------------------------------------------------------------
+// The factorisation of U (or of U P) depends on alpha and beta only; the scalar
+// factor enters only the diagonal.  sym4_prepare computes the factorisation once
+// (for many vectors rotated by the same U, e.g. every kz of one (kx, ky) column),
+// sym4_apply_prep applies it with a scale 1 + ss.
 template <typename T>
-__device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, cx<T> (&x)[5]) {
-  // rho_j = rc_(j+1)/rc_j with rc = (1, 2, sqrt6, 2, 1)
-  const T rho0 = T(2), rho1 = T(1.22474487139158904909864203735294570), rho2 = T(0.81649658092772603273242802490196380),
-          rho3 = T(0.5);
+struct Sym4Prep {
+  cx<T> r, l;   // Taylor-shift coefficients of R and L
+  cx<T> m[4];   // diagonal of D minus 1 at k = 0, 1, 3, 4 (at k = 2 it is 0)
+  int pivot;    // 1: the factorisation of U P (the components are reversed first)
+};
+
+template <typename T>
+__device__ __forceinline__ Sym4Prep<T> sym4_prepare(cx<T> as, cx<T> beta) {
+  Sym4Prep<T> P;
   const cx<T> alpha = mk<T>(T(1) + as.re, as.im);
-  const bool pivot = norm2(beta) > norm2(alpha);
-  cx<T> eps[5];
-  cx<T> r, l;
   const cx<T> one = mk<T>(T(1), T(0));
-  if (!pivot) {
+  P.pivot = norm2(beta) > norm2(alpha);
+  if (!P.pivot) {
     const T q = recip(norm2(alpha));
     const cx<T> ia = mk<T>(alpha.re * q, -alpha.im * q);  // 1/alpha
-    r = beta * ia;
-    l = mk<T>(-beta.re, beta.im) * ia;  // -conj(beta)/alpha
+    P.r = beta * ia;
+    P.l = mk<T>(-beta.re, beta.im) * ia;  // -conj(beta)/alpha
     // a^2 - 1, a^4 - 1, a^-2 - 1, a^-4 - 1 from as = a - 1 without cancellation
     const cx<T> e2 = as * (mk<T>(T(2), T(0)) + as);
     const cx<T> e4 = e2 * (mk<T>(T(2), T(0)) + e2);
@@ -524,32 +531,45 @@ __device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, c
     const cx<T> inv_e2 = mk<T>(one_e2.re * q2, -one_e2.im * q2);
     const cx<T> em2 = mk<T>(-e2.re, -e2.im) * inv_e2;
     const cx<T> em4 = em2 * (mk<T>(T(2), T(0)) + em2);
-    // (1 + e)(1 + s) - 1 = e + s + e s
-    eps[0] = e4 + ss + e4 * ss;
-    eps[1] = e2 + ss + e2 * ss;
-    eps[2] = ss;
-    eps[3] = em2 + ss + em2 * ss;
-    eps[4] = em4 + ss + em4 * ss;
+    P.m[0] = e4;
+    P.m[1] = e2;
+    P.m[2] = em2;
+    P.m[3] = em4;
   } else {
     // U P = [[beta, alpha], [conj(alpha), -conj(beta)]], det -1
     const T q = recip(norm2(beta));
     const cx<T> ia = mk<T>(beta.re * q, -beta.im * q);  // 1/beta
-    r = alpha * ia;
-    l = conj(alpha) * ia;
+    P.r = alpha * ia;
+    P.l = conj(alpha) * ia;
     const cx<T> a2 = beta * beta, a4 = a2 * a2;
     const cx<T> ia2 = ia * ia, ia4 = ia2 * ia2;
-    const cx<T> sc = one + ss;
-    eps[0] = a4 * sc - one;
-    eps[1] = mk<T>(-a2.re, -a2.im) * sc - one;
-    eps[2] = ss;
-    eps[3] = mk<T>(-ia2.re, -ia2.im) * sc - one;
-    eps[4] = ia4 * sc - one;
+    P.m[0] = a4 - one;
+    P.m[1] = mk<T>(-a2.re, -a2.im) - one;
+    P.m[2] = mk<T>(-ia2.re, -ia2.im) - one;
+    P.m[3] = ia4 - one;
+  }
+  return P;
+}
+
+template <typename T>
+__device__ __forceinline__ void sym4_apply_prep(const Sym4Prep<T>& P, cx<T> ss, cx<T> (&x)[5]) {
+  const T rho0 = T(2), rho1 = T(1.22474487139158904909864203735294570), rho2 = T(0.81649658092772603273242802490196380),
+          rho3 = T(0.5);
+  // (1 + m)(1 + s) - 1 = m + s + m s
+  cx<T> eps[5];
+  eps[0] = P.m[0] + ss + P.m[0] * ss;
+  eps[1] = P.m[1] + ss + P.m[1] * ss;
+  eps[2] = ss;
+  eps[3] = P.m[2] + ss + P.m[2] * ss;
+  eps[4] = P.m[3] + ss + P.m[3] * ss;
+  if (P.pivot) {
     cx<T> t0 = x[0], t1 = x[1];
     x[0] = x[4];
     x[1] = x[3];
     x[3] = t1;
     x[4] = t0;
   }
+  const cx<T> r = P.r, l = P.l;
   const cx<T> rr0 = rho0 * r, rr1 = rho1 * r, rr2 = rho2 * r, rr3 = rho3 * r;
   const cx<T> lr0 = rho0 * l, lr1 = rho1 * l, lr2 = rho2 * l, lr3 = rho3 * l;
   // R: Taylor shift, x_j += r rho_j x_(j+1), i = 0..3, j = 3..i
@@ -577,6 +597,11 @@ __device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, c
   x[1] = cfma(lr3, x[0], x[1]);
   x[2] = cfma(lr2, x[1], x[2]);
   x[1] = cfma(lr3, x[0], x[1]);
+}
+
+template <typename T>
+__device__ __forceinline__ void sym4_apply_inc(cx<T> as, cx<T> beta, cx<T> ss, cx<T> (&x)[5]) {
+  sym4_apply_prep<T>(sym4_prepare<T>(as, beta), ss, x);
 }
 
 // cos(x) - 1 and sin(x)/x without cancellation or division by zero.
@@ -702,13 +727,17 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
 // h = exp(i phi) R^H g' and k = -i Sigma h (Sigma = sin(c2 S d)/S, C = cos(c2 S d)):
 //   g = C h + (rho/5) k - A00 A conj(k) + 2 c_rho psi + 2 (c_F.f) psi + 2 conj(z) A conj(psi)
 // where the scalar sensitivities collect the dependence through rho, F, A00, S^2:
-//   q_phi = Im(g'^H psi'), m_a = Im(h^H f_a b), M = J_r(omega)^T m (omega = c1 d F,
-//   J_r the right Jacobian of the rotation exponential), q_C = Re(h^H psi),
-//   q_Sig = -Im(h^H w), q_w = Re(k^H psi)/5, z_w = -k^H A conj(psi),
-//   q_S = C'(S^2) q_C + Sigma'(S^2) q_Sig,
+//   q_phi = Im(g'^H psi') = Im(h^H b) (the map is unitary), m_a = Im(h^H f_a b),
+//   M = J_r(omega)^T m (omega = c1 d F, J_r the right Jacobian of the rotation
+//   exponential), q_C = Re(h^H psi), q_Sig = -Im(h^H w), q_w = Re(k^H psi)/5,
+//   z_w = -k^H A conj(psi), q_S = C'(S^2) q_C + Sigma'(S^2) q_Sig,
 //   c_rho = d c0' q_phi + q_w + q_S 2 rho/25, z = z_w - q_S (2/5) conj(A00), c_F = c1 d M.
 // Parameter partials (added to acc): dJ/dOmega (through the rotated trap, dVdO),
 // dJ/dc0, dJ/dc1, dJ/dc2.
+// The forward output psi' itself is never formed (q_phi uses h and b), and w and
+// A conj(psi) are recomputed from psi where needed, so that few values are live at
+// once: the forward point (psi, b), the adjoint vector (g, turned into h in place)
+// and scalars.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5], double V, double dVdO,
@@ -731,20 +760,16 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
   cosm1_sinc<T>(c2d * S, cm1, snc);
   const T C = T(1) + cm1;
   const T Sig = c2d * snc;
-  // Sigma'(S^2) = (c2 d C - Sigma)/(2 S^2), series -(c2 d)^3/6 (1 - x^2/10) for small x = c2 d S
-  const T x2 = c2d * c2d * S2;
-  const T Sigp = x2 < (sizeof(T) == 4 ? T(1e-3) : T(1e-6)) ? -(c2d * c2d * c2d) / T(6) * (T(1) - x2 / T(10))
-                                                           : (c2d * C - Sig) / (T(2) * S2);
-  const T Cp = -T(0.5) * c2d * Sig;
-  cx<T> Ab[5], w[5], b[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
+  // (A conj psi)_i = (-1)^i conj(psi_(4-i)) / sqrt5 and w_i = rho/5 psi_i - A00 (A conj psi)_i
+  auto Ab = [&](int i) {
     cx<T> ab = conj(p[4 - i]);
     if (i & 1) ab = mk<T>(-ab.re, -ab.im);
-    Ab[i] = r5i * ab;  // (A conj psi)_i
-    w[i] = rho5 * p[i] - A00 * Ab[i];
-    b[i] = p[i] + (cm1 * p[i] + Sig * mul_i(w[i]));
-  }
+    return r5i * ab;
+  };
+  auto wv = [&](int i) { return rho5 * p[i] - A00 * Ab(i); };
+  cx<T> b[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) b[i] = p[i] + (cm1 * p[i] + Sig * mul_i(wv(i)));
   // rotation and phase (as in nl_point)
   const T Fabs = sqrt_nn(norm2(Fp) + Fz * Fz);
   const T hc1d = T(0.5 * K.c1 * K.d);
@@ -756,24 +781,20 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
   double pcm1, psn;
   phase_inc(K.d * (V + K.c0p * (double)rho), pcm1, psn);
   const cx<T> phs = mk<T>((T)pcm1, (T)(-psn));
-  // psi' and h = exp(i phi) R^H g'
-  cx<T> out[5], h[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) { out[i] = b[i]; h[i] = g[i]; }
-  sym4_apply_inc<T>(as, beta, phs, out);
-  sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(phs), h);
+  // h = exp(i phi) R^H g', in place
+  sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(phs), g);
+  // q_phi = Im(h^H b); m_a = Im(h^H f_a b)
   double qphi = 0.0;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) qphi += (double)g[i].re * out[i].im - (double)g[i].im * out[i].re;
-  // m_a = Im(h^H f_a b)
+  for (int i = 0; i < 5; ++i) qphi += (double)g[i].re * b[i].im - (double)g[i].im * b[i].re;
   cx<T> up = mk<T>(T(0), T(0)), um = mk<T>(T(0), T(0)), uz = mk<T>(T(0), T(0));
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
-    up = up + (T(2) * w4[l]) * cmulc(h[l], b[l + 1]);
-    um = um + (T(2) * w4[l]) * cmulc(h[l + 1], b[l]);
+    up = up + (T(2) * w4[l]) * cmulc(g[l], b[l + 1]);
+    um = um + (T(2) * w4[l]) * cmulc(g[l + 1], b[l]);
   }
 #pragma unroll
-  for (int l = 0; l < 5; ++l) uz = uz + ml[l] * cmulc(h[l], b[l]);
+  for (int l = 0; l < 5; ++l) uz = uz + ml[l] * cmulc(g[l], b[l]);
   const T mx = T(0.5) * (up.im + um.im);
   const T my = -T(0.5) * (up.re - um.re);
   const T mz = uz.im;
@@ -797,41 +818,43 @@ __device__ __forceinline__ void nl_point_adj(const cx<T> (&p)[5], cx<T> (&g)[5],
   const T cx1 = oy * mz - oz * my, cy1 = oz * mx - ox * mz, cz1 = ox * my - oy * mx;
   const T cx2 = oy * cz1 - oz * cy1, cy2 = oz * cx1 - ox * cz1, cz2 = ox * cy1 - oy * cx1;
   const T Mx = mx + ja * cx1 + jb * cx2, My = my + ja * cy1 + jb * cy2, Mz = mz + ja * cz1 + jb * cz2;
-  // sensitivities through b
-  T qC = T(0), qSig = T(0);
-  cx<T> k[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const cx<T> hp = cmulc(h[i], p[i]);
-    const cx<T> hw = cmulc(h[i], w[i]);
-    qC += hp.re;
-    qSig -= hw.im;
-    k[i] = mk<T>(Sig * h[i].im, -Sig * h[i].re);  // -i Sigma h
-  }
-  T qw = T(0);
+  // sensitivities through b; k_i = -i Sigma h_i
+  T qC = T(0), qSig = T(0), qw = T(0);
   cx<T> zw = mk<T>(T(0), T(0));
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    qw += cmulc(k[i], p[i]).re;
-    zw = zw - cmulc(k[i], Ab[i]);
+    const cx<T> k = mk<T>(Sig * g[i].im, -Sig * g[i].re);
+    qC += cmulc(g[i], p[i]).re;
+    qSig -= cmulc(g[i], wv(i)).im;
+    qw += cmulc(k, p[i]).re;
+    zw = zw - cmulc(k, Ab(i));
   }
   qw *= T(0.2);
+  // Sigma'(S^2) = (c2 d C - Sigma)/(2 S^2), series -(c2 d)^3/6 (1 - x^2/10) for small x = c2 d S
+  const T x2 = c2d * c2d * S2;
+  const T Sigp = x2 < (sizeof(T) == 4 ? T(1e-3) : T(1e-6)) ? -(c2d * c2d * c2d) / T(6) * (T(1) - x2 / T(10))
+                                                           : (c2d * C - Sig) / (T(2) * S2);
+  const T Cp = -T(0.5) * c2d * Sig;
   const T qS = Cp * qC + Sigp * qSig;
   const T crho = T(K.d * K.c0p * qphi) + qw + qS * (T(2) * rho / T(25));
   const cx<T> z = zw - (T(0.4) * qS) * conj(A00);
   const T cFx = c1d * Mx, cFy = c1d * My, cFz = c1d * Mz;
   const cx<T> cpm = mk<T>(cFx, -cFy), cpp = mk<T>(cFx, cFy);  // c_Fx -/+ i c_Fy
   const cx<T> zc2 = T(2) * conj(z);
+  cx<T> gn[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    cx<T> ak = conj(k[4 - i]);
+    const cx<T> k = mk<T>(Sig * g[i].im, -Sig * g[i].re);
+    cx<T> ak = mk<T>(Sig * g[4 - i].im, Sig * g[4 - i].re);  // conj(k_(4-i))
     if (i & 1) ak = mk<T>(-ak.re, -ak.im);
-    cx<T> r = C * h[i] + rho5 * k[i] - A00 * (r5i * ak) + (T(2) * crho) * p[i] + zc2 * Ab[i];
+    cx<T> r = C * g[i] + rho5 * k - A00 * (r5i * ak) + (T(2) * crho) * p[i] + zc2 * Ab(i);
     cx<T> fpsi = (cFz * ml[i]) * p[i];
     if (i < 4) fpsi = fpsi + w4[i] * (cpm * p[i + 1]);
     if (i > 0) fpsi = fpsi + w4[i - 1] * (cpp * p[i - 1]);
-    g[i] = r + T(2) * fpsi;
+    gn[i] = r + T(2) * fpsi;
   }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) g[i] = gn[i];
   acc[0] += K.d * dVdO * qphi;                                                  // Omega (trap)
   acc[1] += K.d * (double)rho * qphi;                                           // c0
   acc[2] += K.d * ((double)Fp.re * Mx + (double)Fp.im * My + (double)Fz * Mz);  // c1

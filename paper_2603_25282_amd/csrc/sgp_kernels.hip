@@ -44,6 +44,32 @@ hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e
   }
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic sum of block partials: block q adds part[b nq + q] over b; thread t
+// takes b = t, t + 256, ... in order, then a fixed pairwise tree over the threads.
+// The order does not depend on timing, so repeated calls give bitwise equal sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, long nb, int nq,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (long b = t; b < nb; b += 256) s += part[b * nq + q];
+  red[t] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[q] = red[0];
+}
+
+hipError_t launch_sum_partials(const double* part, long nb, int nq, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)nq), dim3(256), 0, st, part, nb, nq, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, const int* n, const double* L,
                                int dim, double Omega, double gamma, double d, hipStream_t st) {

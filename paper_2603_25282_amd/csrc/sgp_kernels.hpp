@@ -13,7 +13,8 @@ enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, 
        // transforms along x (for the lab-frame Algorithm 1 mode)
        X_SHEAR = 11, C_SHEAR = 12, X_FWD = 13, X_INV = 14 };
 enum { NGRAD = 5 };  // adjoint parameter slots: gamma, Omega, c0, c1, c2
-enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2 };
+// observables passes; OBS_JX / OBS_JY: the x-line and y-column parts of <u, J_z v>
+enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2, OBS_JX = 3, OBS_JY = 4 };
 enum { CLOCK_ARG = 0, CLOCK_DEVICE = 1 };
 enum { NOBS = 28 };  // partial sums per block of the observables kernels
 
@@ -94,6 +95,9 @@ hipError_t launch_pass(int kind, void* psi, const PassArgs& a, int n, int e, hip
                        const hipEvent_t* ev = nullptr);
 template <typename T>
 hipError_t launch_obs(int kind, const void* psi, const PassArgs& a, int n, int e, double* part, hipStream_t st);
+// Deterministic sum of block partials: out[q] = sum over b < nb of part[b nq + q],
+// q < nq, in a fixed order (one block per q).
+hipError_t launch_sum_partials(const double* part, long nb, int nq, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_build_tables(void* cs, void* kin_x, void* kin_y, void* kin_z, const int* n, const double* L,
                                int dim, double Omega, double gamma, double d, hipStream_t st);

@@ -208,13 +208,16 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       K.c2 = a.c2;
       double ct, st;
       trap_angle(a, ct, st);
+      // (y, z) indices of the block's first line (uniform); the block's W lines follow it
+      const int iz0 = a.dim == 3 ? line0 / a.ny : 0;
+      const int iy0 = line0 - iz0 * a.ny;
       for (int pt = tid; pt < W * N; pt += NT) {
         const int pc = pt / N, j = pt % N;
         const int line = (int)line0 + pc;  // y + ny z (< 2^31 for every supported grid)
-        int iy = line, iz = 0;
-        if (a.dim == 3) {
-          iz = line / a.ny;
-          iy = line - iz * a.ny;
+        int iy = iy0 + pc, iz = iz0;
+        while (iy >= a.ny) {
+          iy -= a.ny;
+          iz += 1;
         }
         const double x = -a.L[0] + j * a.h[0];
         const double y = -a.L[1] + iy * a.h[1];
@@ -255,7 +258,49 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       // 1/N^d as a (hi, lo) pair: exact for powers of two, compensated otherwise
       const T norm_lo = T(a.norm - (double)norm);
       const int nxx = (int)a.ncols;
+      if constexpr (KIND == C_PROP) {
+        if (a.dim == 3) {
+          // z-lines: the spin part of the propagator and the kinetic phase along x and
+          // y belong to the column (kx, ky), the same for every kz of it; each is
+          // prepared once per column and shared through LDS
+          __shared__ Sym4Prep<T> cprep[W];
+          __shared__ cx<T> ckin[W];
+          if (tid < W) {
+            const int kx = kx0 + tid < nxx ? kx0 + tid : 0;
+            const int px = kx < nxx / 2 ? kx : kx - nxx;
+            const int pq = (int)o < a.n_q / 2 ? (int)o : (int)o - a.n_q;
+            const int qidx = kx * a.n_q + (int)o;
+            const T Cm1 = cs[2 * qidx], S = cs[2 * qidx + 1];
+            const cx<T> as = mk<T>(Cm1, -S * Om);
+            const cx<T> beta = mk<T>(S * ga * T(px * a.nu_scale_a), -S * ga * T(pq * a.nu_scale_q));
+            cprep[tid] = sym4_prepare<T>(as, beta);
+            const cx<T> ka = kin_a[kx], ko = kin_o[o];
+            ckin[tid] = ka + ko + ka * ko;
+          }
+          __syncthreads();
+          for (int pt = tid; pt < W * N; pt += NT) {
+            const int pc = pt / N, kl = pt % N;
+            const cx<T> ka = ckin[pc], kl1 = kin_l[kl];
+            const cx<T> ss = ka + kl1 + ka * kl1;  // kinetic phase - 1
+            cx<T> p[5];
+            if (norm_lo == T(0)) {
+#pragma unroll
+              for (int cc = 0; cc < 5; ++cc) p[cc] = norm * lx[pt * 5 + cc];
+            } else {
+#pragma unroll
+              for (int cc = 0; cc < 5; ++cc)
+                p[cc] = mk<T>(kmul<T>(norm, norm_lo, lx[pt * 5 + cc].re), kmul<T>(norm, norm_lo, lx[pt * 5 + cc].im));
+            }
+            sym4_apply_prep<T>(cprep[pc], ss, p);
+#pragma unroll
+            for (int cc = 0; cc < 5; ++cc) lx[pt * 5 + cc] = p[cc];
+          }
+        }
+      }
       for (int pt = tid; pt < W * N; pt += NT) {
+        if constexpr (KIND == C_PROP) {
+          if (a.dim == 3) break;  // done above
+        }
         const int pc = pt / N, kl = pt % N;
         const int kx = kx0 + pc < nxx ? kx0 + pc : 0;
         const int px = kx < nxx / 2 ? kx : kx - nxx;
@@ -283,9 +328,14 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         const cx<T> kl1 = kin_l[kl];
         const cx<T> ss = ka + kl1 + ka * kl1;  // kinetic phase - 1
         cx<T> p[5];
+        if (norm_lo == T(0)) {
 #pragma unroll
-        for (int cc = 0; cc < 5; ++cc)
-          p[cc] = mk<T>(kmul<T>(norm, norm_lo, lx[pt * 5 + cc].re), kmul<T>(norm, norm_lo, lx[pt * 5 + cc].im));
+          for (int cc = 0; cc < 5; ++cc) p[cc] = norm * lx[pt * 5 + cc];
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < 5; ++cc)
+            p[cc] = mk<T>(kmul<T>(norm, norm_lo, lx[pt * 5 + cc].re), kmul<T>(norm, norm_lo, lx[pt * 5 + cc].im));
+        }
         if constexpr (KIND == C_ADJ) {
           // P^H = P(-d): same (C - 1), S -> -S, conjugate kinetic phase
           sym4_apply_inc<T>(conj(as), mk<T>(-beta.re, -beta.im), conj(ss), p);
@@ -468,13 +518,18 @@ __global__ __launch_bounds__(320) void k_pass_batched(const int2* __restrict__ i
 // the weights (1, sqrt6/2, sqrt6/2, 1) on both off-diagonals, K = -M above and +M
 // below the diagonal.
 // ---------------------------------------------------------------------------
+// OBS_JX / OBS_JY: with u = a.fwd (same layout), the parts of <u, J_z v>, v = psi,
+// J_z = L_z + F_z, L_z = -i (x d_y - y d_x): sums of conj(u) (i y d_x + F_z) v along
+// x-lines and of conj(u) (-i x d_y) v along y-columns, real and imaginary parts in
+// slots 0 and 1.
 template <typename T, int N, int E, int W, int KIND>
 __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict__ psi, PassArgs a,
                                                          double* __restrict__ part) {
   constexpr int TL = N / E;
   constexpr int NT = W * 5 * TL;
   constexpr int LS = PadLine<N>::size;
-  constexpr bool XL = KIND == OBS_X;
+  constexpr bool XL = KIND == OBS_X || KIND == OBS_JX;
+  constexpr bool JZ = KIND == OBS_JX || KIND == OBS_JY;
   constexpr int TILE = 2 * W * N * 5;
   constexpr int XCH = W * 5 * LS;
   constexpr int BUF = TILE > XCH ? TILE : XCH;
@@ -550,10 +605,38 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
     } else {
       on = kx0 + pc < a.ncols;
       x = -a.L[0] + (kx0 + pc) * a.h[0];
-      y = KIND == OBS_Y ? -a.L[1] + j * a.h[1] : 0.0;
+      y = (KIND == OBS_Y || KIND == OBS_JY) ? -a.L[1] + j * a.h[1] : 0.0;
       z = 0.0;
     }
     if (!on) continue;
+    if constexpr (JZ) {
+      // u at this point (global memory), v and its derivative from the tile
+      const cx<T>* u = reinterpret_cast<const cx<T>*>(a.fwd);
+      long ub;
+      if constexpr (XL) ub = (line0 + pc) * (long)N * 5 + (long)j * 5;
+      else ub = o * a.outer_stride + (kx0 + pc) * 5 + (long)j * a.stride;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc) {
+        const double ur = u[ub + cc].re, ui = u[ub + cc].im;
+        const double vr = lx[pt * 5 + cc].re, vi = lx[pt * 5 + cc].im;
+        const double dr = lx[W * N * 5 + pt * 5 + cc].re, di = lx[W * N * 5 + pt * 5 + cc].im;
+        // (J v) at the point: x-lines i y d_x v + m v (m = 2 - cc), columns -i x d_y v
+        double jr, ji;
+        if constexpr (XL) {
+          jr = -y * di + (2 - cc) * vr;
+          ji = y * dr + (2 - cc) * vi;
+        } else {
+          jr = x * di;
+          ji = -x * dr;
+        }
+        sr += ur * jr + ui * ji;  // conj(u) (J v)
+        si += ur * ji - ui * jr;
+      }
+      acc[0] += sr;
+      acc[1] += si;
+      continue;
+    }
     double pr[5], pi[5], dr[5], di[5];
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
@@ -753,7 +836,7 @@ static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t
 template <typename T, int N, int E, int KIND>
 static hipError_t obs_n(const cx<T>* psi, const PassArgs& a, double* part, hipStream_t st) {
   constexpr int W = obs_lines_per_block(N, E);
-  constexpr bool XL = KIND == OBS_X;
+  constexpr bool XL = KIND == OBS_X || KIND == OBS_JX;
   long nblocks = XL ? (a.nlines + W - 1) / W : ((a.ncols + W - 1) / W) * a.nouter;
   hipLaunchKernelGGL((k_obs<T, N, E, W, KIND>), dim3((unsigned)nblocks), dim3(W * 5 * (N / E)), 0, st, psi, a,
                      part);
@@ -765,7 +848,10 @@ static hipError_t obs_kind(int kind, const cx<T>* psi, const PassArgs& a, double
   switch (kind) {
     case OBS_X: return obs_n<T, N, E, OBS_X>(psi, a, part, st);
     case OBS_Y: return obs_n<T, N, E, OBS_Y>(psi, a, part, st);
-    default: return obs_n<T, N, E, OBS_Z>(psi, a, part, st);
+    case OBS_Z: return obs_n<T, N, E, OBS_Z>(psi, a, part, st);
+    case OBS_JX: return obs_n<T, N, E, OBS_JX>(psi, a, part, st);
+    case OBS_JY: return obs_n<T, N, E, OBS_JY>(psi, a, part, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -70,6 +70,7 @@ def lib():
     L.sgp_plan_widths.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int]
     L.sgp_rotation_map.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int]
     L.sgp_diagnostics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.sgp_jz_inner.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
     L.sgp_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sgp_get_plan.argtypes = [vp, ctypes.c_int, ip]
     L.sgp_autotune.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
@@ -87,7 +88,7 @@ def exported_symbols():
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
             "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
             "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune", "sgp_rotation_map",
-            "sgp_diagnostics",
+            "sgp_diagnostics", "sgp_jz_inner",
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
             "sgp_ensemble_set_plan", "sgp_ensemble_get_plan", "sgp_ensemble_autotune",
@@ -200,6 +201,12 @@ class Solver:
         out = (ctypes.c_double * 4)()
         _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
         return np.array(out[:])
+
+    def jz_inner(self, u, v):
+        """<u, J_z v>_h (sgp_jz_inner) as a Python complex."""
+        out = (ctypes.c_double * 2)()
+        _check(lib().sgp_jz_inner(self._ctx, self._psi_ptr(u), self._psi_ptr(v), out), self._ctx)
+        return complex(out[0], out[1])
 
     def diagnostics(self, psi):
         """sgp_diagnostics as a dict: mass, energy, magnetization, lz, delta_x,
