@@ -32,9 +32,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--dtype", default="complex64", choices=["complex64", "complex128"])
     ap.add_argument("--workload", default="2d", choices=["2d", "3d", "3d-256", "ensemble", "paper-eff"],
-                    help="2d: 512^2 TS4 (default); 3d: 128^3 TS4; 3d-256: the 3d workload at 256^3 "
-                         "(a state larger than the Infinity Cache; forward and pass timings only); "
-                         "ensemble: 96 grids; paper-eff: the paper's timing table")
+                    help="2d: 512^2 TS4 (default; with the 3D 128^3, complex128 and ensemble legs beside it); "
+                         "3d: 128^3 TS4 alone; 3d-256: the 3d workload at 256^3 (a state larger than the "
+                         "Infinity Cache; forward and pass timings only); ensemble: 96 grids; paper-eff: the "
+                         "paper's timing table")
+    ap.add_argument("--only-primary", action="store_true",
+                    help="measure the named workload only (no 3D / complex128 / ensemble legs beside it)")
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=50)
@@ -52,6 +55,209 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+class Single:
+    """One single-grid workload in one element type: solver, initial state and the
+    measurements of run() (forward throughput, dominant-pass roofline, bytes model,
+    copy ceiling, fwd+adjoint); error() compares a fresh run with the oracle."""
+
+    def __init__(self, cfg, dtype, a, plan_arg):
+        import torch
+        from paper_2603_25282_amd import inputs as I
+        from paper_2603_25282_amd.sgp import Solver
+        self.cfg, self.dtype, self.a = cfg, dtype, a
+        self.esz = 8 if dtype == "complex64" else 16
+        self.psi0 = I.initial_state(cfg)
+        self.s = Solver(cfg.shape, cfg.L, cfg.params, dtype=dtype)
+        self.s.build_propagator(cfg.tau, cfg.order)
+        self.dev = lambda: torch.from_numpy(Solver.to_device_layout(self.psi0)).to(
+            self.s.torch_dtype).to(self.s.device).contiguous()
+        psi = self.dev()
+        if plan_arg == "auto":
+            self.s.autotune(psi, cfg.order, steps=20)
+        elif plan_arg != "default":
+            self.s.set_plan([int(x) for x in plan_arg.split(",")])
+        self.plan = self.s.get_plan()
+        del psi
+
+    def run(self, steps, warmup, pass_reps, adjoint_steps, K, copy_ceiling=True):
+        import torch
+        from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, SgpError
+        cfg, s = self.cfg, self.s
+        npts, esz = cfg.points, self.esz
+        psi = self.dev()
+
+        # each pass's share of a step, from the start/end events stamped by the
+        # dispatches of its launches inside whole steps of the step schedule (on a
+        # scratch copy of the state); back-to-back launches of one pass for reference.
+        # Measured before the timed region, so that the GPU is busy up to it.
+        scratch = psi.clone()
+        passes = {"xpass": SGP_PASS_X, "ypass": SGP_PASS_Y} if cfg.dim == 2 else \
+            {"xpass": SGP_PASS_X, "ypass_fwd": SGP_PASS_Y, "zpass": SGP_PASS_Z, "ypass_inv": SGP_PASS_YINV}
+        pair, iso = {}, {}
+        for name, pk in passes.items():
+            s.time_pass(scratch, pk, 4, in_steps=True)
+            pair[name] = s.time_pass(scratch, pk, pass_reps, in_steps=True)
+            iso[name] = s.time_pass(scratch, pk, pass_reps)
+        del scratch
+
+        s.time = 0.0
+        mass0 = float(s.observables(psi)[0])
+        s.step(psi, warmup)  # also captures the step graphs
+        torch.cuda.synchronize()
+        # the library runs on torch's current stream (the Solver was created on it), so
+        # these events bracket the timed region on the kernels' own stream
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        s.step(psi, steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        region_ms = ev0.elapsed_time(ev1)
+        gps = npts * steps / elapsed
+        finite = bool(torch.isfinite(torch.view_as_real(psi)).all().item())
+        # the flow conserves mass exactly; what changes is rounding (None when the
+        # state is no longer finite: the observables report an error)
+        try:
+            mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
+        except SgpError:
+            mass_change = None
+        out = {"value": gps, "unit": "gp-steps/s", "steps": steps, "ms_per_step": elapsed * 1e3 / steps,
+               "ms_per_step_events": region_ms / steps, "plan": self.plan, "finite": finite,
+               "mass_rel_change": mass_change}
+
+        # dominant kernel and its average launch duration in the timed region: the
+        # event-timed step split by the passes' shares, per launch
+        # algorithmic bytes per grid point per launch: read + write 5 components, plus
+        # the (C - 1, S) propagator table (2 reals per (x, y) wavevector) on the pass
+        # that applies it (3D: the z-pass reads it once per z-line, nz times smaller)
+        table_b = 2 * esz // 2
+        per_point = {"xpass": 2 * 5 * esz, "ypass": 2 * 5 * esz + (table_b if cfg.dim == 2 else 0),
+                     "ypass_fwd": 2 * 5 * esz, "zpass": 2 * 5 * esz, "ypass_inv": 2 * 5 * esz}
+        lps = 3 if cfg.order == 4 else 1  # launches of each pass per step (merged nonlinear substeps)
+        step_ms = region_ms / steps
+        tot = sum(pair[k] * lps for k in passes)
+        times = {k: step_ms * pair[k] / tot for k in passes}  # per launch, in the timed region
+        dom = max(times, key=lambda k: times[k])
+        bytes_launch = per_point[dom] * npts
+        achieved = bytes_launch / (times[dom] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": stored_traffic(cfg.name, self.dtype, dom, self.plan),
+                           "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,
+                           "pass_ms": times, "pass_ms_in_step": pair, "pass_ms_back_to_back": iso}
+        bpp = sum(per_point[k] * lps for k in passes)
+        out["bytes_model"] = {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9,
+                              "frac": bpp * gps / 1e9 / HBM_PEAK_GBS}
+        if copy_ceiling:
+            # the plain-copy ceiling at this state size: device copies of the state back
+            # and forth between two buffers (each copy reads what the previous one wrote,
+            # as the passes do), timed with events on torch's stream; 2 x state bytes each
+            cp = [psi.clone(), torch.empty_like(psi)]
+            for i in range(6):
+                cp[(i + 1) % 2].copy_(cp[i % 2])
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ncp = 50
+            c0.record()
+            for i in range(ncp):
+                cp[(i + 1) % 2].copy_(cp[i % 2])
+            c1.record()
+            torch.cuda.synchronize()
+            cms = c0.elapsed_time(c1) / ncp
+            cbytes = 2 * psi.numel() * psi.element_size()
+            out["roofline"]["copy_ceiling"] = {"GB_per_s": cbytes / (cms * 1e-3) / 1e9, "ms_per_copy": cms,
+                                               "frac_of_copy": achieved / (cbytes / (cms * 1e-3) / 1e9)}
+            del cp
+        del psi
+        if adjoint_steps > 0:
+            out["fwd_adjoint"] = self.fwd_adjoint(adjoint_steps, K)
+        return out
+
+    def fwd_adjoint(self, n_adj, K):
+        """Forward with checkpoints every K steps + backward (recompute with stores and
+        reverse sweep) through autograd.evolve on this workload's prebuilt solver (no
+        setup inside the timed region), the loss gradient a fixed random direction."""
+        import torch
+        from paper_2603_25282_amd.autograd import evolve
+        cfg, s = self.cfg, self.s
+        p0 = self.dev().requires_grad_(True)
+        prm = cfg.params
+        par = torch.tensor([prm[4], prm[3], prm[0], prm[1], prm[2]], dtype=torch.float64, requires_grad=True)
+        gen = torch.Generator(device=s.device).manual_seed(7)
+        gdir = torch.randn(p0.shape, dtype=s.torch_dtype, device=s.device, generator=gen)
+
+        def fwd_bwd():
+            out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, n_adj, order=cfg.order, K=K, solver=s)
+            J = torch.sum((torch.conj(gdir) * out).real)
+            J.backward()
+
+        fwd_bwd()  # warmup
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            p0.grad = None
+            par.grad = None
+            t0 = time.perf_counter()
+            fwd_bwd()
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        ta = sorted(runs)[1]
+        ok = bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())
+        del p0, gdir
+        torch.cuda.empty_cache()
+        return {"value": self.cfg.points * n_adj / ta, "unit": "gp-steps/s", "steps": n_adj, "K": K,
+                "ms_per_step": ta * 1e3 / n_adj, "median_of": 3, "grad_finite": ok}
+
+    def error(self, ref, nsteps):
+        """Relative l2 distance of the GPU state after nsteps steps (one call, from the
+        initial state at t = 0) to the oracle's state `ref` after the same steps."""
+        import torch
+        from paper_2603_25282_amd.sgp import Solver
+        q = self.dev()
+        self.s.time = 0.0
+        self.s.step(q, nsteps)
+        torch.cuda.synchronize()
+        got = Solver.from_device_layout(q.cpu().numpy().astype(np.complex128))
+        return {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "steps": nsteps,
+                "vs": "FP64 CPU oracle, same initial state and steps"}
+
+
+def stored_traffic(name, dtype, kernel, plan):
+    """HBM bytes per launch of a pass from the committed counter summary, when its
+    device-source hash and plan match the running build (else None)."""
+    tpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    if not os.path.exists(tpath):
+        return None
+    try:
+        tr = json.load(open(tpath))
+        key = f"{name}:{dtype}:{kernel}"
+        if key in tr and tr[key].get("source_hash") == source_hash() and tr[key].get("plan") == plan:
+            return tr[key]["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
+def oracle_sample(cfg, psi0, budget_s, chunk, max_steps=None, fixed_steps=None):
+    """The FP64 oracle on the workload from its initial state, in chunks of steps
+    continuing each other until about budget_s of CPU work (or fixed_steps):
+    returns (steps, seconds, final state)."""
+    import oracle
+    k, tc, u = 0, 0.0, psi0
+    while (fixed_steps is None and tc < budget_s and (max_steps is None or k < max_steps)) or \
+            (fixed_steps is not None and k < fixed_steps):
+        n = chunk if fixed_steps is None else min(chunk, fixed_steps - k)
+        t0 = time.perf_counter()
+        u = oracle.evolve(u, cfg.L, cfg.params, cfg.order, cfg.tau, n, t0=k * cfg.tau)
+        tc += time.perf_counter() - t0
+        k += n
+    return k, tc, u
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -61,11 +267,11 @@ def main():
     import torch
 
     if a.workload == "ensemble":
-        return bench_ensemble(a)
+        return print(json.dumps(bench_ensemble(a, headline=True)), flush=True)
     if a.workload == "paper-eff":
         return bench_paper_efficiency(a)
     from paper_2603_25282_amd import inputs as I
-    from paper_2603_25282_amd.sgp import SGP_PASS_X, SGP_PASS_Y, SGP_PASS_YINV, SGP_PASS_Z, SgpError, Solver
+    from paper_2603_25282_amd.sgp import Solver
 
     cfg = {"2d": I.C2, "3d": I.C3, "3d-256": I.C3_256}[a.workload]
     if a.workload == "3d-256":
@@ -74,167 +280,61 @@ def main():
         # minutes per step
         a.adjoint_steps = a.lab_steps = 0
         a.no_cpu_baseline = True
-    esz = 8 if a.dtype == "complex64" else 16
-    npts = cfg.points
-    psi0 = I.initial_state(cfg)
-    s = Solver(cfg.shape, cfg.L, cfg.params, dtype=a.dtype)
-    s.build_propagator(cfg.tau, cfg.order)
-    psi = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).contiguous()
-    if a.plan == "auto":
-        s.autotune(psi, cfg.order, steps=20)
-    elif a.plan != "default":
-        s.set_plan([int(x) for x in a.plan.split(",")])
-    plan = s.get_plan()
+    legs = not a.only_primary and a.workload == "2d"
 
-    mass0 = float(s.observables(psi)[0])
-    # warmup (also captures the step graph)
-    s.step(psi, a.warmup)
-    torch.cuda.synchronize()
-    # the library runs on torch's current stream (the Solver was created on it), so
-    # these events bracket the timed region on the kernels' own stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    s.step(psi, a.steps)
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    region_ms = ev0.elapsed_time(ev1)
-    gps = npts * a.steps / elapsed
-    finite = bool(torch.isfinite(torch.view_as_real(psi)).all().item())
-    # the flow conserves mass exactly; what changes is rounding (None when the
-    # state is no longer finite: the observables report an error)
-    try:
-        mass_change = float(s.observables(psi)[0]) / mass0 - 1.0
-    except SgpError:
-        mass_change = None
-
-    # dominant kernel and its average launch duration in the timed region: each
-    # pass's share of a step from the start/end events stamped by the dispatches of
-    # its launches inside whole steps (on a scratch copy of the state), times the
-    # event-timed step; back-to-back launches of one pass for reference
-    scratch = psi.clone()
-    passes = {"xpass": SGP_PASS_X, "ypass": SGP_PASS_Y} if cfg.dim == 2 else \
-        {"xpass": SGP_PASS_X, "ypass_fwd": SGP_PASS_Y, "zpass": SGP_PASS_Z, "ypass_inv": SGP_PASS_YINV}
-    # algorithmic bytes per grid point per launch: read + write 5 components, plus
-    # the (C - 1, S) propagator table (2 reals per (x, y) wavevector) on the pass
-    # that applies it (3D: the z-pass reads it once per z-line, nz times smaller)
-    table_b = 2 * esz // 2
-    per_point = {"xpass": 2 * 5 * esz, "ypass": 2 * 5 * esz + (table_b if cfg.dim == 2 else 0),
-                 "ypass_fwd": 2 * 5 * esz, "zpass": 2 * 5 * esz, "ypass_inv": 2 * 5 * esz}
-    launches_per_step = {"xpass": 3, "ypass": 3, "ypass_fwd": 3, "zpass": 3, "ypass_inv": 3}
-    pair, iso = {}, {}
-    for name, pk in passes.items():
-        s.time_pass(scratch, pk, 4, in_steps=True)
-        pair[name] = s.time_pass(scratch, pk, a.pass_reps, in_steps=True)
-        iso[name] = s.time_pass(scratch, pk, a.pass_reps)
-    step_ms = region_ms / a.steps
-    tot = sum(pair[k] * launches_per_step[k] for k in passes)
-    times = {k: step_ms * pair[k] / tot for k in passes}  # per launch, in the timed region
-    dom = max(times, key=lambda k: times[k] * launches_per_step[k])
-    bytes_launch = per_point[dom] * npts
-    achieved = bytes_launch / (times[dom] * 1e-3) / 1e9
-    traffic = None
-    tpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        try:
-            tr = json.load(open(tpath))
-            key = f"{cfg.name}:{a.dtype}:{dom}"
-            if key in tr and tr[key].get("source_hash") == source_hash() and tr[key].get("plan") == plan:
-                traffic = tr[key]["bytes_per_launch"]
-        except Exception:
-            traffic = None
-
+    log(f"primary {cfg.name} {a.dtype}")
+    prim = Single(cfg, a.dtype, a, a.plan)
+    r = prim.run(a.steps, a.warmup, a.pass_reps, a.adjoint_steps, a.K)
     out = {
         "metric": f"5-comp grid-point-steps/s fwd ({cfg.dim}D {cfg.shape[0]}^{cfg.dim} TS{cfg.order})",
-        "value": gps,
+        "value": r["value"],
         "unit": "gp-steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": elapsed * 1e3 / a.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if a.dtype == "complex64" else "f64",
         "data": "synthetic (seeded Gaussian + noise initial state)",
         "config": {"workload": cfg.name, "grid": list(cfg.shape), "L": cfg.L, "scheme": f"TS{cfg.order}",
-                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "plan": plan, "finite": finite,
-                   "mass_rel_change": mass_change},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": times[dom], "algorithmic_bytes_per_launch": bytes_launch,
-                     "pass_ms": times, "pass_ms_in_step": pair, "pass_ms_back_to_back": iso,
-                     "timing": "avg_launch_ms = event-timed step x the pass's share of a step / its launches per "
-                               "step; shares from pass_ms_in_step, the mean duration of the pass's launches inside "
-                               "pass_reps steps of the step schedule, each timed by start/end events that its "
-                               "dispatch stamps"},
+                   "tau": cfg.tau, "params": list(cfg.params), "state": a.dtype, "plan": r["plan"],
+                   "finite": r["finite"], "mass_rel_change": r["mass_rel_change"]},
+        "roofline": r["roofline"],
+        "bytes_model": r["bytes_model"],
     }
-    # whole-step bandwidth of the bytes model (R round trips of the state per step)
-    out["bytes_model"] = {"bytes_per_gp_step": sum(per_point[k] * launches_per_step[k] for k in passes),
-                          "GB_per_s": sum(per_point[k] * launches_per_step[k] for k in passes) * gps / 1e9}
+    if "fwd_adjoint" in r:
+        out["fwd_adjoint"] = r["fwd_adjoint"]
 
-    # the plain-copy ceiling at this state size: device copies of the state back and
-    # forth between two buffers (each copy reads what the previous one wrote, as the
-    # passes do), timed with events on torch's stream; 2 x state bytes per copy
-    cp = [psi.clone(), torch.empty_like(psi)]
-    for i in range(6):
-        cp[(i + 1) % 2].copy_(cp[i % 2])
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ncp = 50
-    c0.record()
-    for i in range(ncp):
-        cp[(i + 1) % 2].copy_(cp[i % 2])
-    c1.record()
-    torch.cuda.synchronize()
-    cms = c0.elapsed_time(c1) / ncp
-    cbytes = 2 * psi.numel() * psi.element_size()
-    out["roofline"]["copy_ceiling"] = {
-        "GB_per_s": cbytes / (cms * 1e-3) / 1e9, "ms_per_copy": cms, "bytes_per_copy": cbytes,
-        "dominant_kernel_frac_of_copy": achieved / (cbytes / (cms * 1e-3) / 1e9),
-        "what": "ping-pong device copy of the state (torch copy_), the rate a pass that only moved "
-                "its bytes would reach at this size"}
-    del cp
-
-    if a.adjoint_steps > 0:
-        # forward with checkpoints every K steps + backward (recompute with stores and
-        # reverse sweep), the loss gradient being a fixed random direction
-        from paper_2603_25282_amd.autograd import evolve
-        n_adj = a.adjoint_steps
-        p0 = torch.from_numpy(Solver.to_device_layout(psi0)).to(s.torch_dtype).to(s.device).requires_grad_(True)
-        prm = cfg.params
-        par = torch.tensor([prm[4], prm[3], prm[0], prm[1], prm[2]], dtype=torch.float64, requires_grad=True)
-        gdir = torch.randn(p0.shape, dtype=s.torch_dtype, device=s.device)
-
-        def fwd_bwd():
-            out = evolve(p0, par, cfg.shape, cfg.L, prm[5:8], cfg.tau, n_adj, order=cfg.order, K=a.K, plan=plan)
-            J = torch.sum((torch.conj(gdir) * out).real)
-            J.backward()
-
-        fwd_bwd()  # warmup
-        torch.cuda.synchronize()
-        runs = []
-        for _ in range(3):
-            p0.grad = None
-            t0 = time.perf_counter()
-            fwd_bwd()
-            torch.cuda.synchronize()
-            runs.append(time.perf_counter() - t0)
-        ta = sorted(runs)[1]
-        out["fwd_adjoint"] = {"metric": "5-comp grid-point-steps/s fwd+adjoint", "value": npts * n_adj / ta,
-                              "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj,
-                              "runs_ms_per_step": [r * 1e3 / n_adj for r in runs], "median_of": 3,
-                              "grad_finite": bool(torch.isfinite(torch.view_as_real(p0.grad)).all().item())}
+    # the other element type of the same workload, and the metric's 3D shape in both
+    others = []
+    if legs:
+        other = "complex128" if a.dtype == "complex64" else "complex64"
+        others.append(("2d_" + ("c128" if other == "complex128" else "c64"), cfg, other))
+        others.append(("3d_c64", I.C3, "complex64"))
+        others.append(("3d_c128", I.C3, "complex128"))
+    sub = {}
+    for key, c, dt in others:
+        log(f"leg {key}: {c.name} {dt}")
+        w = Single(c, dt, a, "auto" if a.plan == "auto" else "default")
+        # a steadier timed region than a few steps: at least 100 steps (the primary
+        # line keeps exactly the requested steps)
+        rr = w.run(max(a.steps, 100), a.warmup, a.pass_reps, a.adjoint_steps, a.K, copy_ceiling=(c.dim == 3))
+        rr["workload"] = c.name
+        rr["metric"] = f"5-comp grid-point-steps/s fwd ({c.dim}D {c.shape[0]}^{c.dim} TS{c.order}), {dt}"
+        sub[key] = (w, rr)
+        out[key] = rr
 
     if a.lab_steps > 0:
         # Algorithm 1 run literally (lab frame): the like-for-like form of the paper's
         # own step, with the rotation mapping before and after every linear substep
+        log("lab-frame Algorithm 1")
         sl = Solver(cfg.shape, cfg.L, cfg.params, dtype=a.dtype)
         sl.set_frame("lab")
         sl.build_propagator(cfg.tau, cfg.order)
-        sl.set_plan(plan)
-        pl = torch.from_numpy(Solver.to_device_layout(psi0)).to(sl.torch_dtype).to(sl.device).contiguous()
+        sl.set_plan(r["plan"])
+        pl = torch.from_numpy(Solver.to_device_layout(prim.psi0)).to(sl.torch_dtype).to(sl.device).contiguous()
         sl.step(pl, 2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -242,14 +342,15 @@ def main():
         torch.cuda.synchronize()
         tl = time.perf_counter() - t0
         out["lab_frame_algorithm1"] = {
-            "value": npts * a.lab_steps / tl, "unit": "gp-steps/s", "ms_per_step": tl * 1e3 / a.lab_steps,
+            "value": cfg.points * a.lab_steps / tl, "unit": "gp-steps/s", "ms_per_step": tl * 1e3 / a.lab_steps,
             "steps": a.lab_steps, "finite": bool(torch.isfinite(torch.view_as_real(pl)).all().item())}
         del sl, pl
 
     if a.unfused_steps > 0 and cfg.dim == 2:
         # the plain unfused FP64 GPU step (PyTorch operations) on the same workload
-        ub = UnfusedFP64(cfg.shape, cfg.L, cfg.params, s.device)
-        u = torch.from_numpy(psi0).to(s.device)
+        log("unfused FP64 step")
+        ub = UnfusedFP64(cfg.shape, cfg.L, cfg.params, prim.s.device)
+        u = torch.from_numpy(prim.psi0).to(prim.s.device)
         u = ub.evolve(u, cfg.order, cfg.tau, 2)  # warmup (tables, FFT plans)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -257,26 +358,26 @@ def main():
         torch.cuda.synchronize()
         tu = time.perf_counter() - t0
         out["baseline_unfused_fp64"] = {
-            "value": npts * a.unfused_steps / tu, "unit": "gp-steps/s", "ms_per_step": tu * 1e3 / a.unfused_steps,
-            "steps": a.unfused_steps, "speedup_of_value": gps / (npts * a.unfused_steps / tu),
-            "finite": bool(torch.isfinite(torch.view_as_real(u)).all().item()),
-            "what": "plain FP64 step in PyTorch-ROCm operations (hipFFT over the grid, batched 5x5 products, "
-                    "elementwise nonlinear flow), same scheme and workload"}
+            "value": cfg.points * a.unfused_steps / tu, "unit": "gp-steps/s",
+            "ms_per_step": tu * 1e3 / a.unfused_steps, "steps": a.unfused_steps,
+            "speedup_of_value": r["value"] / (cfg.points * a.unfused_steps / tu),
+            "finite": bool(torch.isfinite(torch.view_as_real(u)).all().item())}
         del ub, u
+        torch.cuda.empty_cache()
+
+    if legs:
+        log("ensemble leg")
+        out["ensemble"] = bench_ensemble(a, headline=False)
 
     if not a.no_cpu_baseline:
-        # the FP64 oracle on the same workload from the same initial state, in chunks
-        # of steps continuing each other until about 15 s of CPU work (or the given
-        # number of steps)
+        # the FP64 oracle on the same workload from the same initial state (about 15 s
+        # of CPU work, or the given number of steps): the CPU baseline, and the
+        # reference of the error of every GPU result of this workload after as many steps
         import oracle
+        log("oracle sample (primary workload)")
         chunk = 10 if cfg.dim == 2 else 1
-        k, tc, u = 0, 0.0, psi0
-        while (a.cpu_sample_steps is None and tc < 15.0) or (a.cpu_sample_steps is not None and k < a.cpu_sample_steps):
-            t0 = time.perf_counter()
-            u = oracle.evolve(u, cfg.L, cfg.params, cfg.order, cfg.tau, chunk, t0=k * cfg.tau)
-            tc += time.perf_counter() - t0
-            k += chunk
-        out["cpu_baseline"] = {"value": npts * k / tc, "unit": "gp-steps/s", "cores": oracle.num_threads(),
+        k, tc, uref = oracle_sample(cfg, prim.psi0, 15.0, chunk, fixed_steps=a.cpu_sample_steps)
+        out["cpu_baseline"] = {"value": cfg.points * k / tc, "unit": "gp-steps/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
                                "sample": f"{k} TS{cfg.order} steps of the same workload from the same initial state "
                                          f"(FP64, own FFT) in {tc:.1f} s",
@@ -284,31 +385,48 @@ def main():
         # the same oracle on one core, a shorter sample (one step)
         nthr = oracle.num_threads()
         oracle.set_threads(1)
-        k1 = 1
         t0 = time.perf_counter()
-        oracle.evolve(psi0, cfg.L, cfg.params, cfg.order, cfg.tau, k1)
+        oracle.evolve(prim.psi0, cfg.L, cfg.params, cfg.order, cfg.tau, 1)
         t1c = time.perf_counter() - t0
         oracle.set_threads(nthr)
-        out["cpu_baseline"]["one_core"] = {"value": npts * k1 / t1c, "unit": "gp-steps/s", "cores": 1,
-                                           "sample": f"{k1} TS{cfg.order} steps in {t1c:.1f} s"}
+        out["cpu_baseline"]["one_core"] = {"value": cfg.points / t1c, "unit": "gp-steps/s", "cores": 1,
+                                           "sample": f"1 TS{cfg.order} step in {t1c:.1f} s"}
+        out["error_vs_oracle"] = prim.error(uref, k)
+        out["config"]["rel_l2_vs_oracle"] = out["error_vs_oracle"]["rel_l2"]
+        out["config"]["rel_l2_steps"] = k
+        for key, (w, rr) in sub.items():
+            if w.cfg is cfg:
+                rr["error_vs_oracle"] = w.error(uref, k)
+        if any(w.cfg is not cfg for w, _ in sub.values()):
+            c3 = I.C3
+            log("oracle sample (3D workload)")
+            k3, tc3, u3 = oracle_sample(c3, sub["3d_c64"][0].psi0, 10.0, 1, max_steps=10,
+                                        fixed_steps=a.cpu_sample_steps)
+            for key, (w, rr) in sub.items():
+                if w.cfg is c3:
+                    rr["error_vs_oracle"] = w.error(u3, k3)
+            out["3d_c64"]["cpu_oracle"] = {"value": c3.points * k3 / tc3, "unit": "gp-steps/s",
+                                           "cores": oracle.num_threads(), "sample": f"{k3} TS4 steps in {tc3:.1f} s"}
     if a.calib_copy_mb > 0:
-        src = torch.empty(a.calib_copy_mb * 2 ** 20, dtype=torch.uint8, device=s.device)
+        src = torch.empty(a.calib_copy_mb * 2 ** 20, dtype=torch.uint8, device=prim.s.device)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = src.numel()
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, separators=(",", ":")), flush=True)
 
 
-def bench_ensemble(a):
+def bench_ensemble(a, headline=True):
     """96 independent 2D grids (32 x 128^2, 48 x 256^2, 16 x 384^2 on [-12, 12]^2,
     per-instance Omega, gamma, c1, c2), TS2, tau = 1e-3, advanced together by the
-    batched passes; plans autotuned per size and axis before the timed region."""
+    batched passes; plans autotuned per size and axis before the timed region.
+    Returns the contract line (headline) or the leg's object."""
     import torch
     from paper_2603_25282_amd import inputs as I
     from paper_2603_25282_amd.sgp import Ensemble, Solver
     insts = I.ensemble_instances()
-    ens = Ensemble([c.shape for c in insts], [c.L for c in insts], [c.params for c in insts], dtype=a.dtype)
+    dtype = a.dtype if headline else "complex64"
+    ens = Ensemble([c.shape for c in insts], [c.L for c in insts], [c.params for c in insts], dtype=dtype)
     psis = [torch.from_numpy(Solver.to_device_layout(I.initial_state(c))).to(ens.torch_dtype).cuda().contiguous()
             for c in insts]
     ens.build_propagator(insts[0].tau, insts[0].order)
@@ -350,17 +468,28 @@ def bench_ensemble(a):
             torch.cuda.synchronize()
             runs.append(time.perf_counter() - t0)
         ta = sorted(runs)[1]
-        adj = {"metric": "5-comp grid-point-steps/s fwd+adjoint (batched ensemble)", "value": npts * n_adj / ta,
-               "unit": "gp-steps/s", "steps": n_adj, "K": a.K, "ms_per_step": ta * 1e3 / n_adj, "median_of": 3}
+        adj = {"value": npts * n_adj / ta, "unit": "gp-steps/s", "steps": n_adj, "K": a.K,
+               "ms_per_step": ta * 1e3 / n_adj, "median_of": 3}
+        del p0, gdir
     bpp = 80 + 88  # TS2: one X-pass and one Y-pass per step (state read + write, table entry)
-    print(json.dumps({
-        "metric": "5-comp grid-point-steps/s ensemble (96 2D grids, TS2)", "value": gps, "unit": "gp-steps/s",
+    plans = {str(k): list(v) for k, v in ens.plans().items()}
+    del psis, ens
+    torch.cuda.empty_cache()
+    leg = {"metric": "5-comp grid-point-steps/s ensemble (96 2D grids, TS2)", "value": gps, "unit": "gp-steps/s",
+           "steps": steps, "ms_per_step": el * 1e3 / steps, "points": npts, "plans": plans, "finite": finite,
+           "bytes_model": {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9,
+                           "frac": bpp * gps / 1e9 / HBM_PEAK_GBS},
+           "fwd_adjoint": adj}
+    if not headline:
+        return leg
+    return {
+        "metric": leg["metric"], "value": gps, "unit": "gp-steps/s",
         "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": el * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.dtype == "complex64" else "f64",
         "data": "synthetic (seeded random-phase Gaussians, seeded parameters)",
         "config": {"workload": "ensemble-96", "grids": "32x128^2 + 48x256^2 + 16x384^2", "points": npts,
-                   "L": insts[0].L, "scheme": "TS2", "tau": insts[0].tau, "plans": ens.plans(), "finite": finite},
-        "bytes_model": {"bytes_per_gp_step": bpp, "GB_per_s": bpp * gps / 1e9}, "fwd_adjoint": adj}), flush=True)
+                   "L": insts[0].L, "scheme": "TS2", "tau": insts[0].tau, "plans": plans, "finite": finite},
+        "bytes_model": leg["bytes_model"], "fwd_adjoint": adj}
 
 
 # The paper's Table Eff1 (Example "Efficiency"): seconds to advance t = 0 -> 0.1
