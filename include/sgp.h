@@ -120,6 +120,23 @@ int sgp_step(sgp_ctx* ctx, void* psi_dev, long nsteps);
  * Synchronous. */
 int sgp_observables(sgp_ctx* ctx, const void* psi_dev, double out[4]);
 
+/* For callers that cannot allocate device memory or synchronise with the host
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the four values of sgp_observables written to out_dev[0..3]
+ * (caller-owned device memory, 4 doubles), computed by the same kernels with the
+ * same summation order, asynchronously on the context stream.  It allocates
+ * nothing and copies nothing to the host: the block partials and their sums live in
+ * a fixed device scratch array of the library (8 MiB, one per GPU, kept until the
+ * process ends), resolved on the first call on a device (the context's device must
+ * be current).  Grids whose partials need more than that scratch are refused with
+ * SGP_ERR_ARG (every 2D grid and 3D grids up to 256^3 fit; 384^3 and 512^3 do not).
+ * All contexts of a process on one GPU share the scratch and each call leaves its
+ * contents there: calls that may overlap in time on one GPU (contexts on different
+ * streams or host threads) race and must be ordered by the caller.
+ * A state holding a NaN or an infinity yields non-finite out_dev values (no
+ * SGP_ERR_NONFINITE: nothing is read back). */
+int sgp_observables_device(sgp_ctx* ctx, const void* psi_dev, double* out_dev);
+
 /* The inner product <u, J_z v>_h = h^d sum_x sum_l conj(u_l(x)) (J_z v)_l(x) of two
  * states (layout above, the context's element type) with the generator of the
  * rotation about z, J_z = L_z + F_z: L_z = -i (x d_y - y d_x) (Sec. 2, the angular

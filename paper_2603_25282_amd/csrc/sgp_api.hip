@@ -5,6 +5,7 @@
 #include <complex>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -14,6 +15,11 @@
 #include "sgp_kernels.hpp"
 
 using namespace sgp;
+
+// Fixed device scratch of sgp_observables_device (see there): block partials and
+// their sums; one copy per GPU, held until the process ends.
+constexpr size_t kObsScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) double scratch[kObsScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -790,6 +796,78 @@ int jz_inner_impl(sgp_ctx* c, const void* u, const void* v, double out[2]) {
   return SGP_OK;
 }
 
+// The observables with no allocation and no host synchronisation, for callers that
+// cannot allocate (code under graph capture, serving loops): the block partials and
+// their sums live in a file-scope device array of fixed size (one copy per GPU,
+// held until the process ends), and a last kernel combines the sums into the four
+// values on the device.  The array's device address is resolved once per device
+// (hipGetSymbolAddress, with that device current); host code never uses the
+// array's name as an address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int obs_scratch_for_device(sgp_ctx* c, double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, SGP_ERR_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(c, SGP_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SGP_OK;
+}
+
+// out[0..3] = mass, energy, magnetization, <Lz> from the per-axis sums red[axis][q],
+// combined as observables_impl does on the host.
+__global__ void k_obs_combine(const double* __restrict__ red, int dim, double hd, double gamma, double Omega,
+                              double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ekin = 0.0;
+  for (int axis = 0; axis < dim; ++axis) ekin += red[axis * NOBS + 4];
+  const double lz = red[5] + red[NOBS + 5];
+  const double soc = red[6] + red[NOBS + 6];
+  out[0] = hd * red[0];
+  out[2] = hd * red[1];
+  out[3] = hd * lz;
+  out[1] = hd * (ekin + red[2] + red[3] - gamma * soc) - Omega * out[3];
+}
+
+template <typename T>
+int observables_device_impl(sgp_ctx* c, const void* psi, double* sp, long nbmax, double* out_dev) {
+  double* part = sp;
+  double* red = sp + (size_t)NOBS * nbmax;
+  for (int axis = 0; axis < c->g.dim; ++axis) {
+    PassArgs a = base_args(c);
+    if (axis == 0) {
+      a.tw_fwd = c->at(c->off_tw[0][0]);
+      a.tw_inv = c->at(c->off_tw[0][1]);
+      a.nu_scale_l = kPi / c->g.L[0];
+    } else {
+      column_geometry(c, axis, a);
+    }
+    a.s_arg = c->frame == SGP_FRAME_LAB ? 0.0 : c->t;
+    const int kind = axis == 0 ? OBS_X : (axis == 1 ? OBS_Y : OBS_Z);
+    hipError_t e = launch_obs<T>(kind, psi, a, c->g.n[axis], c->elems(axis), part, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "observables launch");
+    e = launch_sum_partials(part, obs_nblocks(c, axis, c->elems(axis)), NOBS, red + axis * NOBS, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "observables reduction");
+  }
+  double hd = 1.0;
+  for (int ax = 0; ax < c->g.dim; ++ax) hd *= 2.0 * c->g.L[ax] / c->g.n[ax];
+  hipLaunchKernelGGL(k_obs_combine, dim3(1), dim3(64), 0, c->st, red, c->g.dim, hd, c->p.gamma, c->p.Omega,
+                     out_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "observables combine");
+  return SGP_OK;
+}
+
 // Rotation mapping of Sec. 3.1 by the three shears of eqs. RSDA1/RSDA2, each a
 // transform along one axis, a phase exp(i nu a w) per coefficient and the inverse
 // transform: dir = +1 gives Phi = M_t Psi, phi_l = exp(-i l Omega t) psi_l(R(t) x);
@@ -1079,6 +1157,23 @@ int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
   if (rc == SGP_OK || rc == SGP_ERR_NONFINITE) std::memcpy(out, all, 4 * sizeof(double));
   return rc;
+}
+
+int sgp_observables_device(sgp_ctx* c, const void* psi, double* out_dev) {
+  if (!c || !psi || !out_dev) return fail(c, SGP_ERR_ARG, "null argument");
+  if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
+  long nbmax = 0;
+  for (int axis = 0; axis < c->g.dim; ++axis) nbmax = std::max(nbmax, obs_nblocks(c, axis, c->elems(axis)));
+  const size_t need = sizeof(double) * NOBS * ((size_t)nbmax + 3);
+  if (need > kObsScratchBytes)
+    return fail(c, SGP_ERR_ARG, "grid too large for sgp_observables_device: its block partials need " +
+                                    std::to_string(need) + " bytes of the fixed " +
+                                    std::to_string(kObsScratchBytes) + "-byte device scratch");
+  double* sp = nullptr;
+  const int rc = obs_scratch_for_device(c, &sp);
+  if (rc != SGP_OK) return rc;
+  return c->dtype == SGP_C64 ? observables_device_impl<float>(c, psi, sp, nbmax, out_dev)
+                             : observables_device_impl<double>(c, psi, sp, nbmax, out_dev);
 }
 
 int sgp_jz_inner(sgp_ctx* c, const void* u, const void* v, double out[2]) {

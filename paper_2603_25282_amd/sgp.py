@@ -88,7 +88,7 @@ def exported_symbols():
             "sgp_observables", "sgp_get_time", "sgp_set_time", "sgp_time_pass", "sgp_set_option", "sgp_destroy",
             "sgp_last_error", "sgp_store_size", "sgp_step_store", "sgp_adjoint_segment", "sgp_adjoint_gradients",
             "sgp_plan_widths", "sgp_set_plan", "sgp_get_plan", "sgp_autotune", "sgp_rotation_map",
-            "sgp_diagnostics", "sgp_jz_inner",
+            "sgp_diagnostics", "sgp_jz_inner", "sgp_observables_device",
             "sgp_ensemble_create", "sgp_ensemble_workspace_size", "sgp_ensemble_set_workspace",
             "sgp_ensemble_build_propagator", "sgp_ensemble_step", "sgp_ensemble_set_option", "sgp_ensemble_destroy",
             "sgp_ensemble_set_plan", "sgp_ensemble_get_plan", "sgp_ensemble_autotune",
@@ -201,6 +201,18 @@ class Solver:
         out = (ctypes.c_double * 4)()
         _check(lib().sgp_observables(self._ctx, self._psi_ptr(psi), out), self._ctx)
         return np.array(out[:])
+
+    def observables_device(self, psi, out):
+        """sgp_observables_device: mass, energy, magnetization and <Lz> written to
+        out[0:4] (a float64 device tensor), asynchronously on the solver's stream, with
+        no allocation and no host synchronisation."""
+        import torch
+        L = lib()
+        L.sgp_observables_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        if out.dtype != torch.float64 or out.numel() < 4 or not out.is_contiguous() or out.device != self.device:
+            raise SgpError("out must be a contiguous float64 tensor of at least 4 values on the solver's device")
+        _check(L.sgp_observables_device(self._ctx, self._psi_ptr(psi), ctypes.c_void_p(out.data_ptr())),
+               self._ctx)
 
     def jz_inner(self, u, v):
         """<u, J_z v>_h (sgp_jz_inner) as a Python complex."""
