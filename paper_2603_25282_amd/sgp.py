@@ -485,15 +485,55 @@ class Ensemble:
         """{n: (x width, y width)} over the instance sizes."""
         return {n: (self.get_plan(n, 0), self.get_plan(n, 1)) for n in sorted({sh[0] for sh in self.shapes})}
 
-    def autotune(self, psis, steps=10):
-        """sgp_ensemble_autotune on scratch copies of psis; returns (plans(), ms per step)."""
+    def plan_key(self, scheme):
+        """JSON plan-cache key: device architecture, the instance sizes with their
+        counts, element type and scheme."""
+        import torch
+        from collections import Counter
+        prop = torch.cuda.get_device_properties(self.device)
+        arch = getattr(prop, "gcnArchName", "") or prop.name
+        sizes = "+".join(f"{k}x{n}^2" for n, k in sorted(Counter(sh[0] for sh in self.shapes).items()))
+        return f"{arch}|ensemble:{sizes}|{str(self.torch_dtype).replace('torch.', '')}|TS{scheme}"
+
+    def autotune(self, psis, steps=10, scheme=None, cache=False):
+        """sgp_ensemble_autotune on scratch copies of psis; returns (plans(), ms per
+        step).  With cache (and the ensemble's scheme), a choice stored in the JSON plan
+        cache (plan_cache_path(), shared with Solver.autotune) for this device, set of
+        instance sizes, element type and scheme is applied without timing (ms None),
+        and a new choice is stored there."""
+        import json
         self._ptrs(psis)
+        key = self.plan_key(scheme) if cache and scheme is not None else None
+        path = plan_cache_path()
+        table = {}
+        if key is not None and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+            if key in table:
+                for n, (ex, ey) in table[key]["plans"].items():
+                    self.set_plan(int(n), 0, int(ex))
+                    self.set_plan(int(n), 1, int(ey))
+                return self.plans(), None
         scratch = [p.clone() for p in psis]
         arr = self._ptrs(scratch)
         ms = ctypes.c_double()
         self._chk(lib().sgp_ensemble_autotune(self._h, arr, int(steps), ctypes.byref(ms)))
         del scratch
-        return self.plans(), ms.value
+        plans = self.plans()
+        if key is not None:
+            table[key] = {"plans": {str(n): list(v) for n, v in plans.items()}, "ms_per_step": ms.value}
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                tmp = path + f".{os.getpid()}.tmp"
+                with open(tmp, "w") as f:
+                    json.dump(table, f, indent=1, sort_keys=True)
+                os.replace(tmp, path)
+            except OSError:
+                pass
+        return plans, ms.value
 
     def close(self):
         if getattr(self, "_h", None):

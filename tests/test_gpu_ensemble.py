@@ -172,3 +172,22 @@ def test_ensemble_autotune():
     err = rel_l2(Solver.from_device_layout(psis[-1].cpu().numpy().astype(np.complex128)), ref)
     print("384 instance after autotune rel l2", err)
     assert err <= 5e-5
+
+
+def test_ensemble_plan_cache(tmp_path, monkeypatch):
+    # the autotuned per-size plans go to the JSON plan cache and a fresh ensemble of
+    # the same sizes takes them from there without timing
+    monkeypatch.setenv("SGP_PLAN_CACHE", str(tmp_path / "plans.json"))
+    insts = I.ensemble_instances(seed=4, n128=2, n256=1, n384=1, L=12.0, order=2, tau=1e-3, steps=0)
+    ens, psis = make(insts, "complex64")
+    ens.build_propagator(1e-3, 2)
+    plans, ms = ens.autotune(psis, steps=3, scheme=2, cache=True)
+    assert ms is not None and ms > 0
+    import json
+    table = json.load(open(tmp_path / "plans.json"))
+    key = ens.plan_key(2)
+    assert key in table and {int(n): tuple(v) for n, v in table[key]["plans"].items()} == plans
+    ens2, psis2 = make(insts, "complex64")
+    ens2.build_propagator(1e-3, 2)
+    plans2, ms2 = ens2.autotune(psis2, steps=3, scheme=2, cache=True)
+    assert ms2 is None and plans2 == plans
