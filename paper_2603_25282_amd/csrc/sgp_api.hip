@@ -261,11 +261,11 @@ hipError_t run_colpass(sgp_ctx* c, hipStream_t st, int mode, int axis, void* psi
   a.kin_o = c->at(c->off_kin[table][1]);
   a.kin_l = c->at(c->off_kin[table][axis]);
   a.d = d;
-  a.advance_clock = (mode == C_PROP) ? 1 : 0;
+  a.advance_clock = (mode == C_PROP || mode == C_FSPIN) ? 1 : 0;
   if (!ev) {
     int pid = -1;
-    if (axis == 1 && (mode == C_PROP || mode == C_FWD)) pid = 1;
-    else if (axis == 2 && mode == C_PROP) pid = 2;
+    if (axis == 1 && (mode == C_PROP || mode == C_FWD || mode == C_FSPIN)) pid = 1;
+    else if (axis == 2 && (mode == C_PROP || mode == C_KIN)) pid = 2;
     else if (axis == 1 && mode == C_INV) pid = 3;
     ev = timing_events(c, pid);
   }
@@ -305,13 +305,19 @@ hipError_t run_colpass_ex(sgp_ctx* c, int kind, int axis, void* psi, int table, 
   return launch_pass<T>(kind, psi, a, c->g.n[axis], c->elems(axis), c->st);
 }
 
-// One exact linear substep on x-transformed data: 2D Y-pass, 3D Y1 + Z + Y2.
+// One exact linear substep on x-transformed data: 2D Y-pass; 3D Y1 (FFT along y, the
+// spin part of the propagator exp(i d Q(nu_p, nu_q)) with the x and y kinetic phases
+// and 1/N^3), Z (FFT along z, the z kinetic phase, inverse FFT) and Y2 (inverse FFT
+// along y).  The spin part depends on (nu_p, nu_q) only (Sec. 3.1, 3D remark), so it
+// commutes with the z transform and runs in the y-pass, whose memory time leaves
+// room for it; the z-pass then works per component.  (The differentiable path,
+// sgp_step_store and the adjoint, keeps the whole propagator in the z-pass.)
 template <typename T>
 hipError_t run_linear(sgp_ctx* c, hipStream_t st, void* psi, int table, double d) {
   if (c->g.dim == 2) return run_colpass<T>(c, st, C_PROP, 1, psi, table, d);
-  hipError_t e = run_colpass<T>(c, st, C_FWD, 1, psi, table, d);
+  hipError_t e = run_colpass<T>(c, st, C_FSPIN, 1, psi, table, d);
   if (e != hipSuccess) return e;
-  e = run_colpass<T>(c, st, C_PROP, 2, psi, table, d);
+  e = run_colpass<T>(c, st, C_KIN, 2, psi, table, d);
   if (e != hipSuccess) return e;
   return run_colpass<T>(c, st, C_INV, 1, psi, table, d);
 }
@@ -492,8 +498,8 @@ hipError_t launch_timed_pass(sgp_ctx* c, void* psi, int pass, bool first, const 
   // X-pass as inside a step: the clock from the device slots (set by the first launch)
   if (pass == 0)
     return run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], first ? CLOCK_ARG : CLOCK_DEVICE, c->t, ev);
-  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FWD, 1, psi, 0, 0.0, ev);
-  if (pass == 2) return run_colpass<T>(c, c->st, C_PROP, 2, psi, 0, 0.0, ev);
+  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FSPIN, 1, psi, 0, 0.0, ev);
+  if (pass == 2) return run_colpass<T>(c, c->st, C_KIN, 2, psi, 0, 0.0, ev);
   return run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0, ev);
 }
 

@@ -38,6 +38,16 @@ template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx
   return mk<T>(acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re);
 }
 
+// x + a x for a factor 1 + a close to 1, with the product a x formed before the sum.
+// In cfma's order the small real part of a (of second order in the angle, for a
+// unit-modulus factor) is added to x alone and rounds away whenever it is below half
+// an ulp of x, always in the same direction, so that repeated unit-modulus factors
+// let |x| grow; formed first, it is a term of a x and its rounding is unbiased.
+template <typename T> __device__ __forceinline__ cx<T> inc_apply(cx<T> a, cx<T> x) {
+  const cx<T> d = a * x;
+  return mk<T>(x.re + d.re, x.im + d.im);
+}
+
 // 1/x.  FP32: the hardware reciprocal estimate (within 1 ulp) refined by one Newton
 // step; FP64: division.  Used only on magnitudes bounded away from 0 and infinity.
 template <typename T>
@@ -555,13 +565,6 @@ template <typename T>
 __device__ __forceinline__ void sym4_apply_prep(const Sym4Prep<T>& P, cx<T> ss, cx<T> (&x)[5]) {
   const T rho0 = T(2), rho1 = T(1.22474487139158904909864203735294570), rho2 = T(0.81649658092772603273242802490196380),
           rho3 = T(0.5);
-  // (1 + m)(1 + s) - 1 = m + s + m s
-  cx<T> eps[5];
-  eps[0] = P.m[0] + ss + P.m[0] * ss;
-  eps[1] = P.m[1] + ss + P.m[1] * ss;
-  eps[2] = ss;
-  eps[3] = P.m[2] + ss + P.m[2] * ss;
-  eps[4] = P.m[3] + ss + P.m[3] * ss;
   if (P.pivot) {
     cx<T> t0 = x[0], t1 = x[1];
     x[0] = x[4];
@@ -583,9 +586,15 @@ __device__ __forceinline__ void sym4_apply_prep(const Sym4Prep<T>& P, cx<T> ss, 
   x[3] = cfma(rr3, x[4], x[3]);
   x[2] = cfma(rr2, x[3], x[2]);
   x[3] = cfma(rr3, x[4], x[3]);
-  // D: x_j += eps_j x_j
+  // D: x_j += eps_j x_j with 1 + eps_j = (1 + m_j)(1 + ss) (m at k = 2 is 0)
+  cx<T> eps[5];
+  eps[0] = P.m[0] + ss + P.m[0] * ss;
+  eps[1] = P.m[1] + ss + P.m[1] * ss;
+  eps[2] = ss;
+  eps[3] = P.m[2] + ss + P.m[2] * ss;
+  eps[4] = P.m[3] + ss + P.m[3] * ss;
 #pragma unroll
-  for (int j = 0; j < 5; ++j) x[j] = cfma(eps[j], x[j], x[j]);
+  for (int j = 0; j < 5; ++j) x[j] = inc_apply(eps[j], x[j]);
   // L: Taylor shift on the reversed vector, x_(4-k) += l rho_k x_(3-k)
   x[1] = cfma(lr3, x[0], x[1]);
   x[2] = cfma(lr2, x[1], x[2]);
@@ -694,14 +703,17 @@ __device__ __forceinline__ void nl_point(cx<T> (&p)[5], double V, const NLCoef& 
   cosm1_sinc<T>(c2d * S, cm1, snc);
   const T snS = c2d * snc;  // sin(c2 S d) / S
   // b = psi + (cos - 1) psi + i snS (rho/5 psi - A00 (A conj psi)_i),
-  // (A conj psi)_i = (-1)^i conj(psi_(4-i)) / sqrt5
+  // (A conj psi)_i = (-1)^i conj(psi_(4-i)) / sqrt5, i.e.
+  // b_i = psi_i + k1 psi_i - k2 (-1)^i conj(psi_(4-i)) with k1 = (cos - 1) + i snS rho/5
+  // and k2 = i snS A00 / sqrt5
+  const cx<T> k1 = mk<T>(cm1, snS * rho5);
+  const cx<T> k2 = mul_i((snS * r5i) * A00);
   cx<T> b[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     cx<T> ab = conj(p[4 - i]);
     if (i & 1) ab = mk<T>(-ab.re, -ab.im);
-    const cx<T> w = rho5 * p[i] - A00 * (r5i * ab);
-    b[i] = p[i] + (cm1 * p[i] + snS * mul_i(w));
+    b[i] = p[i] + (k1 * p[i] - k2 * ab);
   }
   // spin rotation: alpha - 1 = (cos(kappa/2) - 1) - i s F_z, beta = -i s F_-
   const T Fabs = sqrt_nn(norm2(Fp) + Fz * Fz);

@@ -11,7 +11,12 @@ enum { X_FIRST = 0, X_MID = 1, X_LAST = 2, X_NLONLY = 3, C_PROP = 4, C_FWD = 5, 
        // rotation mapping (RSDA shears, Sec. 3.1): FFT, phase exp(i nu a w), inverse FFT
        // along x (w = y of the line) or along y (w = x of the column); and bare
        // transforms along x (for the lab-frame Algorithm 1 mode)
-       X_SHEAR = 11, C_SHEAR = 12, X_FWD = 13, X_INV = 14 };
+       X_SHEAR = 11, C_SHEAR = 12, X_FWD = 13, X_INV = 14,
+       // 3D linear substep with the propagator split by axis (its spin part depends on
+       // (nu_p, nu_q) only, Sec. 3.1's 3D remark, so it commutes with the z transform):
+       // y-lines FFT then exp(-i d (nu_x^2 + nu_y^2)/2) exp(i d Q) / N^3 (C_FSPIN), and
+       // z-lines FFT, exp(-i d nu_z^2/2), inverse FFT per component (C_KIN)
+       C_FSPIN = 15, C_KIN = 16 };
 enum { NGRAD = 5 };  // adjoint parameter slots: gamma, Omega, c0, c1, c2
 // observables passes; OBS_JX / OBS_JY: the x-line and y-column parts of <u, J_z v>
 enum { OBS_X = 0, OBS_Y = 1, OBS_Z = 2, OBS_JX = 3, OBS_JY = 4 };

@@ -70,12 +70,14 @@ template <int KIND> struct KindInfo {
   static constexpr bool XADJ = KIND == XA_FIRST || KIND == XA_MID || KIND == XA_LAST;
   static constexpr bool ADJ = XADJ || KIND == C_ADJ;
   static constexpr bool PW = (XL && !SHEAR && KIND != X_FWD && KIND != X_INV) || KIND == C_PROP ||
-                             KIND == C_ADJ;  // has a pointwise stage (on the LDS tile)
+                             KIND == C_ADJ || KIND == C_FSPIN;  // has a pointwise stage (on the LDS tile)
   // which transforms the pass runs (forward: exp(-i..), inverse: exp(+i..))
   static constexpr bool HF = KIND == X_FIRST || KIND == X_MID || KIND == XA_MID || KIND == XA_LAST ||
-                             KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || SHEAR || KIND == X_FWD;
+                             KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || SHEAR || KIND == X_FWD ||
+                             KIND == C_FSPIN || KIND == C_KIN;
   static constexpr bool HI = KIND == X_MID || KIND == X_LAST || KIND == XA_FIRST || KIND == XA_MID ||
-                             KIND == C_PROP || KIND == C_INV || KIND == C_ADJ || SHEAR || KIND == X_INV;
+                             KIND == C_PROP || KIND == C_INV || KIND == C_ADJ || SHEAR || KIND == X_INV ||
+                             KIND == C_KIN;
 };
 
 // LDS cx<T> values of the staged twiddle tables of a pass (forward table first).
@@ -152,8 +154,18 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
   if constexpr (KIND == X_MID || KIND == X_LAST || KIND == C_INV || KIND == XA_FIRST || KIND == XA_MID ||
                 KIND == X_INV)
     fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, twi, 0);
-  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || KIND == X_FWD || KindInfo<KIND>::SHEAR)
+  if constexpr (KIND == C_PROP || KIND == C_FWD || KIND == C_ADJ || KIND == X_FWD || KindInfo<KIND>::SHEAR ||
+                KIND == C_FSPIN || KIND == C_KIN)
     fft_line<T, N, E, -1, 1, 1, 0>(v, xl, t, twf, 0);
+
+  if constexpr (KIND == C_KIN) {
+    // the kinetic phase along the line, per component: coefficient k times
+    // exp(-i d nu_k^2/2), in increment form (table entry exp(..) - 1)
+    const cx<T>* kin_l = reinterpret_cast<const cx<T>*>(a.kin_l);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[0][m] = inc_apply(kin_l[t + TL * m], v[0][m]);
+    fft_line<T, N, E, +1, 1, 1, 0>(v, xl, t, twi, 0);
+  }
 
   if constexpr (KindInfo<KIND>::SHEAR) {
     // f(.. + a w ..) along the line: coefficient k times exp(i nu_k a w) / N, w the
@@ -308,9 +320,9 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
         int kq;
         int qidx;
         cx<T> ka = kin_a[kx];
-        // table kx-major: a column block reads its entries contiguously (2D) or
-        // one broadcast entry (3D)
-        if (a.dim == 2) {
+        // table kx-major: a column block reads its entries contiguously (2D, and the
+        // 3D y-lines of C_FSPIN) or one broadcast entry (3D z-lines)
+        if (a.dim == 2 || KIND == C_FSPIN) {
           kq = kl;
           qidx = kx * a.n_q + kl;
         } else {
@@ -426,7 +438,7 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       a.clock[2] = sn;
     }
   }
-  if constexpr (KIND == C_PROP) {
+  if constexpr (KIND == C_PROP || KIND == C_FSPIN) {
     if (a.advance_clock && tile == 0 && tid == 0) {
       const double s1 = a.clock[0] + a.d;
       double sn, cn;
@@ -829,6 +841,8 @@ static hipError_t pass_kind(int kind, cx<T>* psi, const PassArgs& a, hipStream_t
     case C_SHEAR: return pass_n<T, N, E, C_SHEAR>(psi, a, st, ev);
     case X_FWD: return pass_n<T, N, E, X_FWD>(psi, a, st, ev);
     case X_INV: return pass_n<T, N, E, X_INV>(psi, a, st, ev);
+    case C_FSPIN: return pass_n<T, N, E, C_FSPIN>(psi, a, st, ev);
+    case C_KIN: return pass_n<T, N, E, C_KIN>(psi, a, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
