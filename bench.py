@@ -77,7 +77,19 @@ class Single:
             self.s.torch_dtype).to(self.s.device).contiguous()
         psi = self.dev()
         if plan_arg == "auto":
-            self.s.autotune(psi, cfg.order, steps=20)
+            # each candidate timed over >= ~25 ms of steps (a 20-step call of a
+            # sub-0.1 ms step is within the run-to-run noise of near-equal plans)
+            import time
+            q = psi.clone()
+            self.s.step(q, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self.s.step(q, 20)
+            torch.cuda.synchronize()
+            guess = (time.perf_counter() - t0) * 1e3 / 20
+            self.s.time = 0.0
+            del q
+            self.s.autotune(psi, cfg.order, steps=max(20, min(400, int(25.0 / max(guess, 1e-3)))))
         elif plan_arg != "default":
             self.s.set_plan([int(x) for x in plan_arg.split(",")])
         self.plan = self.s.get_plan()
@@ -150,10 +162,12 @@ class Single:
         # event-timed step split by the passes' shares, per launch
         # algorithmic bytes per grid point per launch: read + write 5 components, plus
         # the (C - 1, S) propagator table (2 reals per (x, y) wavevector) on the pass
-        # that applies it (2D: the y-pass; 3D: the forward y-pass, once per point)
+        # that applies it: the 2D y-pass reads each entry once; the 3D forward y-pass
+        # reads the N^2-entry table once per z-plane, from L2 after the first plane,
+        # so its HBM share is nz times smaller and left out
         table_b = 2 * esz // 2
         per_point = {"xpass": 2 * 5 * esz, "ypass": 2 * 5 * esz + table_b,
-                     "ypass_fwd": 2 * 5 * esz + table_b, "zpass": 2 * 5 * esz, "ypass_inv": 2 * 5 * esz}
+                     "ypass_fwd": 2 * 5 * esz, "zpass": 2 * 5 * esz, "ypass_inv": 2 * 5 * esz}
         lps = 3 if cfg.order == 4 else 1  # launches of each pass per step (merged nonlinear substeps)
         step_ms = region_ms / steps
         tot = sum(pair[k] * lps for k in passes)
@@ -244,14 +258,23 @@ class Single:
 
 def stored_traffic(name, dtype, kernel, plan):
     """HBM bytes per launch of a pass from the committed counter summary, when its
-    device-source hash and plan match the running build (else None)."""
+    device-source hash and the register plan of the pass's own axis (the kernel
+    depends on that width only) match the running build (else None)."""
     tpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     if not os.path.exists(tpath):
         return None
     try:
         tr = json.load(open(tpath))
         key = f"{name}:{dtype}:{kernel}"
-        if key in tr and tr[key].get("source_hash") == source_hash() and tr[key].get("plan") == plan:
+        ax = {"xpass": 0, "ypass": 1, "ypass_fwd": 1, "ypass_inv": 1, "zpass": 2}[kernel]
+        if key not in tr or tr[key].get("source_hash") != source_hash():
+            return None
+        tp = tr[key].get("plan")
+        # the 3D forward y-pass and z-pass kernels also depend on the linear
+        # substep's split (the plan's fourth entry)
+        if kernel in ("ypass_fwd", "zpass") and len(plan) > 3 and (len(tp) <= 3 or tp[3] != plan[3]):
+            return None
+        if tp[ax] == plan[ax]:
             return tr[key]["bytes_per_launch"]
     except Exception:
         pass

@@ -237,14 +237,26 @@ int sgp_time_pass(sgp_ctx* ctx, void* psi_dev, int pass, int reps, double* avg_m
  *   and drops the captured step graph; call it between steps, not concurrently
  *   with work on the context's stream.
  * sgp_get_plan: the current width of `axis`.
+ * Pseudo-axis SGP_PLAN_LINEAR (3D contexts only; SGP_ERR_ARG otherwise): how a
+ *   linear substep's passes split the propagator of eq. sl1, whose spin part
+ *   exp(i d Q) depends on (nu_p, nu_q) only (Sec. 3.1, 3D): 0 (default) = FFT
+ *   along y, then along z the FFT, the whole propagator and the inverse FFT, then
+ *   the inverse FFT along y; 1 = FFT along y with the x and y kinetic phases and
+ *   the spin part applied there, then along z the FFT, the z kinetic phase and the
+ *   inverse FFT, then the inverse FFT along y.  Same results up to rounding; with
+ *   sgp_set_plan(ctx, SGP_PLAN_LINEAR, 0 or 1) and sgp_get_plan likewise.  The
+ *   differentiable path (sgp_step_store, the adjoint) always uses split 0.
  * sgp_autotune: picks the fastest combination of the axes' widths (every
- *   combination, at most 9 in 2D and 27 in 3D) by timing `steps` steps of the
+ *   combination, at most 9 in 2D and 27 in 3D, in 3D for both linear-substep
+ *   splits) by timing `steps` steps of the
  *   sgp_step path for each, after one untimed call of `steps` steps; psi_dev is
  *   a device state in the layout of sgp_step; it is advanced by every timed and
  *   untimed step (pass a scratch copy).  Needs the workspace and the propagator;
  *   the context time is left unchanged.  Writes the chosen widths to elems_out
  *   (0 for axes beyond dim) and, if ms_per_step is not NULL, the fastest time per
- *   step in ms.  The choice stays set on the context. */
+ *   step in ms.  The choice (and in 3D the split, read back with sgp_get_plan)
+ *   stays set on the context. */
+enum { SGP_PLAN_LINEAR = 3 };
 int sgp_plan_widths(int n, int dtype, int* out, int max_out);
 int sgp_set_plan(sgp_ctx* ctx, int axis, int elems);
 int sgp_get_plan(const sgp_ctx* ctx, int axis, int* elems);

@@ -99,6 +99,9 @@ struct sgp_ctx {
 
   // register plan width E of the passes along each axis
   int plan_e[3] = {0, 0, 0};
+  // 3D linear substep: 0 = FFT y, whole propagator in the z-pass, iFFT y (default);
+  // 1 = FFT y with the spin part in the y-pass, z kinetic phase in the z-pass, iFFT y
+  int lin_split = 0;
   // 0: evolve Phi in the rotating frame (default); 1: Algorithm 1 literally (lab frame)
   int frame = 0;
 
@@ -315,9 +318,9 @@ hipError_t run_colpass_ex(sgp_ctx* c, int kind, int axis, void* psi, int table, 
 template <typename T>
 hipError_t run_linear(sgp_ctx* c, hipStream_t st, void* psi, int table, double d) {
   if (c->g.dim == 2) return run_colpass<T>(c, st, C_PROP, 1, psi, table, d);
-  hipError_t e = run_colpass<T>(c, st, C_FSPIN, 1, psi, table, d);
+  hipError_t e = run_colpass<T>(c, st, c->lin_split ? C_FSPIN : C_FWD, 1, psi, table, d);
   if (e != hipSuccess) return e;
-  e = run_colpass<T>(c, st, C_KIN, 2, psi, table, d);
+  e = run_colpass<T>(c, st, c->lin_split ? C_KIN : C_PROP, 2, psi, table, d);
   if (e != hipSuccess) return e;
   return run_colpass<T>(c, st, C_INV, 1, psi, table, d);
 }
@@ -498,10 +501,17 @@ hipError_t launch_timed_pass(sgp_ctx* c, void* psi, int pass, bool first, const 
   // X-pass as inside a step: the clock from the device slots (set by the first launch)
   if (pass == 0)
     return run_xpass<T>(c, c->st, X_MID, psi, c->dprop[0], first ? CLOCK_ARG : CLOCK_DEVICE, c->t, ev);
-  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : C_FSPIN, 1, psi, 0, 0.0, ev);
-  if (pass == 2) return run_colpass<T>(c, c->st, C_KIN, 2, psi, 0, 0.0, ev);
+  if (pass == 1) return run_colpass<T>(c, c->st, c->g.dim == 2 ? C_PROP : (c->lin_split ? C_FSPIN : C_FWD), 1, psi, 0,
+                                       0.0, ev);
+  if (pass == 2) return run_colpass<T>(c, c->st, c->lin_split ? C_KIN : C_PROP, 2, psi, 0, 0.0, ev);
   return run_colpass<T>(c, c->st, C_INV, 1, psi, 0, 0.0, ev);
 }
+
+// Events that a dispatch stamps for per-kernel timing: without the system-scope
+// fence, so that stamping them does not write back and invalidate the caches
+// between kernels (the graph replay of a step does not either); they are only read
+// by hipEventElapsedTime after a synchronisation on a later event.
+constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
 
 // In-step timing: reps rounds of the passes of one linear + nonlinear substep in
 // step order (2D: y, X; 3D: y, z, inverse y, X); every launch of the timed pass
@@ -512,7 +522,7 @@ int time_pass_in_step(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms)
   const std::vector<int> order = c->g.dim == 2 ? std::vector<int>{1, 0} : std::vector<int>{1, 2, 3, 0};
   std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
   hipError_t e = hipSuccess;
-  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], kTimingEventFlags);
   bool first_x = true;
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     for (int p : order) {
@@ -522,6 +532,7 @@ int time_pass_in_step(sgp_ctx* c, void* psi, int pass, int reps, double* avg_ms)
     }
   double total = 0.0;
   if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
@@ -563,7 +574,7 @@ template <typename T>
 int time_pass_steps(sgp_ctx* c, void* psi, int pass, int nsteps, double* avg_ms) {
   c->tev.assign(2 * (12 * (size_t)nsteps + 8), nullptr);  // more pairs than launches of one pass
   hipError_t e = hipSuccess;
-  for (size_t i = 0; i < c->tev.size() && e == hipSuccess; ++i) e = hipEventCreate(&c->tev[i]);
+  for (size_t i = 0; i < c->tev.size() && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->tev[i], kTimingEventFlags);
   int rc = SGP_OK;
   size_t used = 0;
   if (e == hipSuccess) {
@@ -581,6 +592,7 @@ int time_pass_steps(sgp_ctx* c, void* psi, int pass, int nsteps, double* avg_ms)
   double total = 0.0;
   if (e == hipSuccess && rc == SGP_OK && used > 0) {
     e = hipEventSynchronize(c->tev[2 * used - 1]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     for (size_t i = 0; i < used && e == hipSuccess; ++i) {
       float ms = 0.f;
       e = hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]);
@@ -600,6 +612,14 @@ int time_pass_steps(sgp_ctx* c, void* psi, int pass, int nsteps, double* avg_ms)
 // Register plan of the passes along one axis; the twiddle tables follow the plan.
 template <typename T>
 int set_plan_impl(sgp_ctx* c, int axis, int e) {
+  if (axis == SGP_PLAN_LINEAR && c->g.dim == 3) {
+    if (e != 0 && e != 1) return fail(c, SGP_ERR_ARG, "linear-substep split must be 0 or 1");
+    if (c->lin_split != e) {
+      c->lin_split = e;
+      drop_graph(c);
+    }
+    return SGP_OK;
+  }
   if (axis < 0 || axis >= c->g.dim) return fail(c, SGP_ERR_ARG, "axis out of range");
   if (e == 0) e = default_elems(c->g.n[axis]);
   if (!plan_ok(c->g.n[axis], e, (int)c->esize))
@@ -616,7 +636,8 @@ int set_plan_impl(sgp_ctx* c, int axis, int e) {
 }
 
 // Autotuner: time `steps` whole steps (the sgp_step path, graphs included) for
-// every combination of the axes' plan widths and keep the fastest.  psi is advanced by the timed steps; the context time
+// every combination of the axes' plan widths (in 3D also both linear-substep
+// splits) and keep the fastest.  psi is advanced by the timed steps; the context time
 // is restored.
 template <typename T>
 int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_ms) {
@@ -648,24 +669,31 @@ int autotune_impl(sgp_ctx* c, void* psi, int steps, int out_e[3], double* best_m
   std::vector<int> w[3];
   for (int ax = 0; ax < 3; ++ax) w[ax] = ax < c->g.dim ? plan_widths(c->g.n[ax], (int)c->esize) : std::vector<int>{0};
   int best_e[3] = {c->plan_e[0], c->plan_e[1], c->plan_e[2]};
+  int best_ls = c->lin_split;
   const int start[3] = {c->plan_e[0], c->plan_e[1], c->plan_e[2]};
-  for (int ex : w[0])
-    for (int ey : w[1])
-      for (int ez : w[2]) {
-        if (rc != SGP_OK) break;
-        const int cand[3] = {ex, ey, ez};
-        bool same = true;
-        for (int ax = 0; ax < c->g.dim; ++ax) same = same && cand[ax] == start[ax];
-        if (same) continue;
-        for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, cand[ax]);
-        double ms = 0.0;
-        if (rc == SGP_OK) rc = time_steps(&ms);
-        if (rc == SGP_OK && ms < best) {
-          best = ms;
-          for (int ax = 0; ax < c->g.dim; ++ax) best_e[ax] = cand[ax];
+  const int start_ls = c->lin_split;
+  const int nsplit = c->g.dim == 3 ? 2 : 1;
+  for (int ls = 0; ls < nsplit; ++ls)
+    for (int ex : w[0])
+      for (int ey : w[1])
+        for (int ez : w[2]) {
+          if (rc != SGP_OK) break;
+          const int cand[3] = {ex, ey, ez};
+          bool same = ls == start_ls;
+          for (int ax = 0; ax < c->g.dim; ++ax) same = same && cand[ax] == start[ax];
+          if (same) continue;
+          for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, cand[ax]);
+          if (rc == SGP_OK && c->g.dim == 3) rc = set_plan_impl<T>(c, SGP_PLAN_LINEAR, ls);
+          double ms = 0.0;
+          if (rc == SGP_OK) rc = time_steps(&ms);
+          if (rc == SGP_OK && ms < best) {
+            best = ms;
+            best_ls = ls;
+            for (int ax = 0; ax < c->g.dim; ++ax) best_e[ax] = cand[ax];
+          }
         }
-      }
   for (int ax = 0; ax < c->g.dim && rc == SGP_OK; ++ax) rc = set_plan_impl<T>(c, ax, best_e[ax]);
+  if (rc == SGP_OK && c->g.dim == 3) rc = set_plan_impl<T>(c, SGP_PLAN_LINEAR, best_ls);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->t = t_save;
@@ -1294,6 +1322,10 @@ int sgp_set_plan(sgp_ctx* c, int axis, int elems) {
 }
 
 int sgp_get_plan(const sgp_ctx* c, int axis, int* elems) {
+  if (c && elems && axis == SGP_PLAN_LINEAR && c->g.dim == 3) {
+    *elems = c->lin_split;
+    return SGP_OK;
+  }
   if (!c || !elems || axis < 0 || axis >= c->g.dim) return SGP_ERR_ARG;
   *elems = c->plan_e[axis];
   return SGP_OK;

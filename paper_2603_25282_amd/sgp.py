@@ -25,6 +25,7 @@ SGP_TIME_IN_STEP = 256
 SGP_TIME_STEPS = 512
 SGP_OPT_FRAME = 3
 SGP_FRAME_ROTATING, SGP_FRAME_LAB = 0, 1
+SGP_PLAN_LINEAR = 3
 
 
 class SgpError(RuntimeError):
@@ -268,16 +269,21 @@ class Solver:
         return np.array(out[:])
 
     def get_plan(self):
-        """Plan width E of the passes along x, y (, z)."""
+        """Plan width E of the passes along x, y (, z); in 3D a fourth entry, the
+        linear substep's split (SGP_PLAN_LINEAR: 0 = the whole propagator in the
+        z-pass, 1 = its spin part in the forward y-pass)."""
         e = ctypes.c_int()
         out = []
-        for ax in range(len(self.shape)):
+        for ax in range(len(self.shape)) if len(self.shape) == 2 else (0, 1, 2, SGP_PLAN_LINEAR):
             _check(lib().sgp_get_plan(self._ctx, ax, ctypes.byref(e)), self._ctx)
             out.append(e.value)
         return out
 
     def set_plan(self, widths):
-        """Plan widths per axis (x, y (, z)); 0 = default."""
+        """Plan widths per axis (x, y (, z)); 0 = default; in 3D an optional fourth
+        entry sets the linear substep's split (see get_plan)."""
+        if len(widths) > len(self.shape) + (1 if len(self.shape) == 3 else 0):
+            raise SgpError(f"plan {list(widths)} has too many entries for a {len(self.shape)}D grid")
         for ax, e in enumerate(widths):
             _check(lib().sgp_set_plan(self._ctx, ax, int(e)), self._ctx)
 
@@ -310,7 +316,7 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib().sgp_autotune(self._ctx, self._psi_ptr(scratch), int(steps), out, ctypes.byref(ms)), self._ctx)
         del scratch
-        widths = list(out[:len(self.shape)])
+        widths = self.get_plan()
         if cache:
             table[key] = {"widths": widths, "ms_per_step": ms.value}
             try:

@@ -115,6 +115,16 @@ def test_plan_widths_and_plan_setters_without_device():
     outw = (ctypes.c_int * 3)()
     assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 5, outw, None) == -2  # no workspace yet
     assert L.sgp_autotune(ctx, ctypes.c_void_p(1), 0, outw, None) == -1
+    # the linear-substep split (pseudo-axis 3) exists for 3D contexts only
+    assert L.sgp_set_plan(ctx, 3, 1) == -1 and L.sgp_get_plan(ctx, 3, ctypes.byref(e)) == -1
+    L.sgp_destroy(ctx)
+    rc, ctx = _create(dim=3, n=(32, 32, 16), L=(8.0, 8.0, 8.0))
+    assert rc == 0
+    assert L.sgp_get_plan(ctx, 3, ctypes.byref(e)) == 0 and e.value == 0
+    assert L.sgp_set_plan(ctx, 3, 1) == 0
+    assert L.sgp_get_plan(ctx, 3, ctypes.byref(e)) == 0 and e.value == 1
+    assert L.sgp_set_plan(ctx, 3, 2) == -1 and b"split" in L.sgp_last_error(ctx)
+    assert L.sgp_set_plan(ctx, 4, 0) == -1
     L.sgp_destroy(ctx)
 
 

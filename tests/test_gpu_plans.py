@@ -99,7 +99,9 @@ def test_plans_3d(dtype):
     cfg = I.with_(base, params=tuple(p))
     psi0 = I.initial_state(cfg)
     ref = oracle.evolve(psi0, cfg.L, cfg.params, 4, 1e-3, 4)
-    for widths in [(4, 4, 4), (16, 8, 4), (4, 8, 8), (16, 4, 8)]:
+    # the fourth entry: the linear substep's split (0: whole propagator in the
+    # z-pass; 1: its spin part in the forward y-pass)
+    for widths in [(4, 4, 4, 0), (16, 8, 4, 1), (4, 8, 8, 0), (4, 8, 8, 1), (16, 4, 8, 1), (8, 4, 8, 0)]:
         print(f"case plans 3D {cfg.shape} {dtype} widths={widths}", flush=True)
         got, _, _ = run_plan(cfg, dtype, widths, steps=4)
         err = rel_l2(got, ref)
@@ -176,6 +178,32 @@ def test_autotune_choice_cache_and_parity(tmp_path, monkeypatch):
     # the cache: a second solver takes the stored choice without timing
     table = json.load(open(os.environ["SGP_PLAN_CACHE"]))
     assert table[s.plan_key(4)]["widths"] == widths
+    s2 = Solver(cfg.shape, cfg.L, cfg.params, dtype="complex64")
+    s2.build_propagator(1e-3, 4)
+    w2, ms2 = s2.autotune(to_gpu(s2, psi0), 4)
+    assert w2 == widths and ms2 is None
+
+
+def test_autotune_3d_picks_widths_and_split(tmp_path, monkeypatch):
+    # in 3D the tuner also chooses the linear substep's split; its choice is a
+    # four-entry plan that round-trips through the cache and is correct
+    import torch
+    from paper_2603_25282_amd.sgp import Solver, plan_widths
+    monkeypatch.setenv("SGP_PLAN_CACHE", str(tmp_path / "plans.json"))
+    cfg = I.with_(I.C3, shape=(16, 32, 32), name="tune3d")
+    psi0 = I.initial_state(cfg)
+    s = Solver(cfg.shape, cfg.L, cfg.params, dtype="complex64")
+    s.build_propagator(1e-3, 4)
+    psi = to_gpu(s, psi0)
+    widths, ms = s.autotune(psi, 4, steps=2)
+    print("autotuned 3D", widths, ms, flush=True)
+    assert len(widths) == 4 and widths[3] in (0, 1)
+    assert widths[0] in plan_widths(32) and widths[1] in plan_widths(32) and widths[2] in plan_widths(16)
+    assert s.get_plan() == widths
+    s.step(psi, 3)
+    torch.cuda.synchronize()
+    got = Solver.from_device_layout(psi.cpu().numpy().astype(np.complex128))
+    assert rel_l2(got, oracle.evolve(psi0, cfg.L, cfg.params, 4, 1e-3, 3)) <= 5e-5
     s2 = Solver(cfg.shape, cfg.L, cfg.params, dtype="complex64")
     s2.build_propagator(1e-3, 4)
     w2, ms2 = s2.autotune(to_gpu(s2, psi0), 4)
