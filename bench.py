@@ -266,15 +266,12 @@ def stored_traffic(name, dtype, kernel, plan):
     try:
         tr = json.load(open(tpath))
         key = f"{name}:{dtype}:{kernel}"
-        ax = {"xpass": 0, "ypass": 1, "ypass_fwd": 1, "ypass_inv": 1, "zpass": 2}[kernel]
-        if key not in tr or tr[key].get("source_hash") != source_hash():
-            return None
-        tp = tr[key].get("plan")
         # the 3D forward y-pass and z-pass kernels also depend on the linear
-        # substep's split (the plan's fourth entry)
-        if kernel in ("ypass_fwd", "zpass") and len(plan) > 3 and (len(tp) <= 3 or tp[3] != plan[3]):
-            return None
-        if tp[ax] == plan[ax]:
+        # substep's split (the plan's fourth entry): one entry per split
+        if kernel in ("ypass_fwd", "zpass") and len(plan) > 3:
+            key += f":split{plan[3]}"
+        ax = {"xpass": 0, "ypass": 1, "ypass_fwd": 1, "ypass_inv": 1, "zpass": 2}[kernel]
+        if key in tr and tr[key].get("source_hash") == source_hash() and tr[key].get("plan")[ax] == plan[ax]:
             return tr[key]["bytes_per_launch"]
     except Exception:
         pass

@@ -97,6 +97,29 @@ def test_checkpoint_file_roundtrip(tmp_path):
                                 "frame"}
 
 
+def test_checkpoint_3d_plan_with_split(tmp_path):
+    # a 3D run whose plan includes the linear substep's split (the non-default one):
+    # the file carries all four plan entries and the resumed run is bitwise the same
+    import torch
+    from paper_2603_25282_amd import checkpoint
+    shape, L, n1, n2 = (16, 32, 32), 6.0, 5, 4
+    print(f"case checkpoint 3D split plan {shape}", flush=True)
+    s = Solver(shape, L, PARAMS, dtype="complex64")
+    s.set_plan([4, 8, 4, 1])
+    s.build_propagator(1e-3, 4)
+    psi = to_gpu(s, _state(shape, L, 29))
+    s.step(psi, n1)
+    path = str(tmp_path / "run3d.npz")
+    checkpoint.save(path, s, psi)
+    s.step(psi, n2)
+    torch.cuda.synchronize()
+    s2, psi2 = checkpoint.load(path)
+    assert s2.get_plan() == [4, 8, 4, 1]
+    s2.step(psi2, n2)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, psi2)
+
+
 def test_checkpoint_lab_frame_side_stream(tmp_path):
     # a lab-frame run (Algorithm 1 literally) on a side stream: the file written right
     # after the steps were queued holds the finished state and the frame, so the
