@@ -306,7 +306,9 @@ int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* par
 /* One caller-owned workspace for all instances (tables, twiddles, work lists). */
 int sgp_ensemble_workspace_size(const sgp_ensemble* ens, size_t* bytes);
 int sgp_ensemble_set_workspace(sgp_ensemble* ens, void* dev_ptr, size_t bytes);
-/* FP64 propagator tables of every instance for the common tau and scheme. */
+/* FP64 propagator tables of every instance for the common tau and scheme
+ * (SGP_TS2, SGP_TS4 or SGP_TS6; the step's launch sequence follows the scheme's
+ * composition, Sec. 3.3, as for single grids).  SGP_ERR_ARG for another scheme. */
 int sgp_ensemble_build_propagator(sgp_ensemble* ens, double tau, int scheme);
 /* psi_devs: host array of n_inst device pointers (instance i: [ny][nx][5] complex).
  * Advances every instance by nsteps (common clock).  Asynchronous. */

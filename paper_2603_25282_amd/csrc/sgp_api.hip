@@ -1388,7 +1388,12 @@ struct sgp_ensemble {
   struct Part { int ex, ey, nmax; long off[2], n[2]; };
   std::vector<Part> parts;
   char* ws = nullptr;
-  int nslots = 0;  // PassArgs slots (per instance): see ens_slots()
+  // argument slots of a step (per instance one PassArgs each): the first X-pass,
+  // then one slot per distinct (pass kind, duration, table) of the composition; a
+  // body step and the last step of a call as slot sequences
+  struct Slot { int kind; int table; double d; };
+  std::vector<Slot> slots;
+  std::vector<int> body, tail;
   std::vector<void*> psis;
   bool args_ok = false;
   bool use_graph = true;
@@ -1417,9 +1422,42 @@ int efail(sgp_ensemble* e, int code, const std::string& msg) {
   return code;
 }
 
-// Argument slots of one step: 0 first X, 1 X (a2 or merged in TS2), 2 merged X (TS4),
-// 3 last X, 4 linear with table 0, 5 linear with table 1.
-enum { ES_XFIRST = 0, ES_XMID = 1, ES_XMERGE = 2, ES_XLAST = 3, ES_LIN0 = 4, ES_LIN1 = 5, ES_N = 6 };
+// Most argument slots a composition needs (TS6: first, three inner and one merged
+// X-pass durations, the last X-pass, four propagator tables).
+constexpr int ES_MAX = 12;
+
+// The slots and the body / last-step sequences of the ensemble's composition
+// (Sec. 3.3), from the same Composition as single grids: a body step is
+// L(B[0]) N(A[1]) ... L(B[m-2]) N(A[m-1] + A[0]) (the merged flow), the last step
+// ends with N(A[m-1]); slot 0 is the first N(A[0]) (clock from the host).
+void ens_build_slots(sgp_ensemble* e) {
+  const Composition k = composition(e->scheme);
+  const double tau = e->tau;
+  const size_t m = k.A.size();
+  e->slots.clear();
+  e->body.clear();
+  e->tail.clear();
+  auto slot = [&](int kind, int table, double d) {
+    for (size_t i = 0; i < e->slots.size(); ++i)
+      if (e->slots[i].kind == kind && e->slots[i].table == table && e->slots[i].d == d) return (int)i;
+    e->slots.push_back({kind, table, d});
+    return (int)e->slots.size() - 1;
+  };
+  slot(X_FIRST, -1, k.A[0] * tau);
+  for (size_t j = 0; j + 1 < m; ++j) {
+    const int l = slot(C_PROP, k.tab[j], k.B[j] * tau);
+    e->body.push_back(l);
+    e->tail.push_back(l);
+    if (j + 2 < m) {
+      const int x = slot(X_MID, -1, k.A[j + 1] * tau);
+      e->body.push_back(x);
+      e->tail.push_back(x);
+    } else {
+      e->body.push_back(slot(X_MID, -1, (k.A[m - 1] + k.A[0]) * tau));
+      e->tail.push_back(slot(X_LAST, -1, k.A[m - 1] * tau));
+    }
+  }
+}
 
 void drop_egraph(sgp_ensemble* e) {
   if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
@@ -1429,42 +1467,32 @@ void drop_egraph(sgp_ensemble* e) {
 
 // Build all PassArgs slots for the current state pointers and upload them.
 hipError_t ens_upload_args(sgp_ensemble* e) {
-  std::vector<PassArgs> host((size_t)ES_N * e->n);
-  const double tau = e->tau;
-  double dX[4], dL[2];
-  if (e->scheme == SGP_TS2) {
-    dX[0] = 0.5 * tau; dX[1] = tau; dX[2] = tau; dX[3] = 0.5 * tau;
-    dL[0] = tau; dL[1] = tau;
-  } else {
-    TS4 k;
-    dX[0] = k.a1 * tau; dX[1] = k.a2 * tau; dX[2] = 2.0 * k.a1 * tau; dX[3] = k.a1 * tau;
-    dL[0] = k.b1 * tau; dL[1] = k.b2 * tau;
-  }
+  const size_t ns = e->slots.size();
+  std::vector<PassArgs> host(ns * e->n);
   for (int i = 0; i < e->n; ++i) {
     sgp_ctx* c = e->ctx[i];
-    for (int sl = 0; sl < ES_N; ++sl) {
+    for (size_t sl = 0; sl < ns; ++sl) {
+      const sgp_ensemble::Slot& S = e->slots[sl];
       PassArgs a = base_args(c);
       a.state = e->psis[i];
       a.gacc = (double*)c->at(c->off_gacc);
-      if (sl <= ES_XLAST) {
+      a.d = S.d;
+      if (S.kind != C_PROP) {
         a.tw_fwd = c->at(c->off_tw[0][0]);
         a.tw_inv = c->at(c->off_tw[0][1]);
-        a.d = dX[sl];
-        a.clock_mode = sl == ES_XFIRST ? CLOCK_ARG : CLOCK_DEVICE;
+        a.clock_mode = S.kind == X_FIRST ? CLOCK_ARG : CLOCK_DEVICE;
         a.s_arg = e->t;
         a.n_line = c->g.n[0];
       } else {
-        const int table = sl == ES_LIN0 ? 0 : (e->scheme == SGP_TS2 ? 0 : 1);
         column_geometry(c, 1, a);
-        a.cs = c->at(c->off_cs[table]);
-        a.kin_a = c->at(c->off_kin[table][0]);
-        a.kin_o = c->at(c->off_kin[table][1]);
-        a.kin_l = c->at(c->off_kin[table][1]);
-        a.d = dL[sl - ES_LIN0];
+        a.cs = c->at(c->off_cs[S.table]);
+        a.kin_a = c->at(c->off_kin[S.table][0]);
+        a.kin_o = c->at(c->off_kin[S.table][1]);
+        a.kin_l = c->at(c->off_kin[S.table][1]);
         a.advance_clock = 1;
         a.n_line = c->g.n[1];
       }
-      host[(size_t)sl * e->n + i] = a;
+      host[sl * e->n + i] = a;
     }
   }
   hipError_t r = hipMemcpyAsync(e->ws + e->off_args, host.data(), sizeof(PassArgs) * host.size(),
@@ -1545,9 +1573,8 @@ hipError_t ens_build_items(sgp_ensemble* e) {
 template <typename T>
 hipError_t ens_launch_part(sgp_ensemble* e, const sgp_ensemble::Part& P, hipStream_t st, int slot) {
   const PassArgs* args = (const PassArgs*)(e->ws + e->off_args) + (size_t)slot * e->n;
-  const bool xl = slot <= ES_XLAST;
-  const int kind = slot == ES_XFIRST ? X_FIRST : (slot == ES_XLAST ? X_LAST : (xl ? X_MID : C_PROP));
-  const int ax = xl ? 0 : 1;
+  const int kind = e->slots[slot].kind;
+  const int ax = kind == C_PROP ? 1 : 0;
   const int2* items = (const int2*)(e->ws + e->off_items[ax]);
   return launch_pass_batched<T>(kind, ax == 0 ? P.ex : P.ey, items + P.off[ax], args, P.n[ax], P.nmax, st);
 }
@@ -1585,23 +1612,12 @@ hipError_t ens_run_parts(sgp_ensemble* e, hipStream_t st, const std::vector<int>
   });
 }
 
-// Slots of one body step (after a merged nonlinear substep, ending with the next one)
-// and of the final step.
-std::vector<int> ens_body(int scheme) {
-  if (scheme == SGP_TS2) return {ES_LIN0, ES_XMERGE};
-  return {ES_LIN0, ES_XMID, ES_LIN1, ES_XMID, ES_LIN0, ES_XMERGE};
-}
-std::vector<int> ens_tail(int scheme) {
-  if (scheme == SGP_TS2) return {ES_LIN0, ES_XLAST};
-  return {ES_LIN0, ES_XMID, ES_LIN1, ES_XMID, ES_LIN0, ES_XLAST};
-}
-
 // A forward call: every partition runs its own launch sequence on its own stream
 // (one fork and one join per phase: first pass, graph replays, rest), so passes of
 // different partitions overlap freely.
 template <typename T>
 int ens_step_impl(sgp_ensemble* e, long nsteps) {
-  hipError_t r = ens_run_parts<T>(e, e->st, {ES_XFIRST}, 1);
+  hipError_t r = ens_run_parts<T>(e, e->st, {0}, 1);
   if (r != hipSuccess) return efail(e, SGP_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(r));
   long nbody = nsteps - 1;
   const int G = 16;
@@ -1615,7 +1631,7 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
         return efail(e, SGP_ERR_HIP, "stream create");
       r = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
       if (r != hipSuccess) return efail(e, SGP_ERR_HIP, "graph capture");
-      hipError_t r1 = ens_run_parts<T>(e, e->cap, ens_body(e->scheme), G);
+      hipError_t r1 = ens_run_parts<T>(e, e->cap, e->body, G);
       hipGraph_t g = nullptr;
       r = hipStreamEndCapture(e->cap, &g);
       if (r1 != hipSuccess || r != hipSuccess) {
@@ -1633,8 +1649,8 @@ int ens_step_impl(sgp_ensemble* e, long nsteps) {
   }
   std::vector<int> rest;
   for (long b = 0; b < nbody; ++b)
-    for (int sl : ens_body(e->scheme)) rest.push_back(sl);
-  for (int sl : ens_tail(e->scheme)) rest.push_back(sl);
+    for (int sl : e->body) rest.push_back(sl);
+  for (int sl : e->tail) rest.push_back(sl);
   if ((r = ens_run_parts<T>(e, e->st, rest, 1)) != hipSuccess) return efail(e, SGP_ERR_HIP, "batched launch");
   return SGP_OK;
 }
@@ -1804,7 +1820,7 @@ int sgp_ensemble_create(int n_inst, const sgp_grid* grids, const sgp_params* par
     off += align256(sizeof(int2) * cap);
   }
   e->off_args = off;
-  off += align256(sizeof(PassArgs) * ES_N * n_inst);
+  off += align256(sizeof(PassArgs) * ES_MAX * n_inst);
   e->total = off;
   e->psis.assign(n_inst, nullptr);
   *out = e;
@@ -1836,13 +1852,15 @@ int sgp_ensemble_set_workspace(sgp_ensemble* e, void* dev_ptr, size_t bytes) {
 int sgp_ensemble_build_propagator(sgp_ensemble* e, double tau, int scheme) {
   if (!e) return SGP_ERR_ARG;
   if (!e->ws) return efail(e, SGP_ERR_STATE, "no workspace set");
-  if (scheme != SGP_TS2 && scheme != SGP_TS4) return efail(e, SGP_ERR_ARG, "ensembles run SGP_TS2 or SGP_TS4");
+  if (scheme != SGP_TS2 && scheme != SGP_TS4 && scheme != SGP_TS6)
+    return efail(e, SGP_ERR_ARG, "ensembles run SGP_TS2, SGP_TS4 or SGP_TS6");
   for (int i = 0; i < e->n; ++i) {
     int rc = sgp_build_propagator(e->ctx[i], tau, scheme);
     if (rc != SGP_OK) return efail(e, rc, "instance " + std::to_string(i) + ": " + e->ctx[i]->err);
   }
   e->scheme = scheme;
   e->tau = tau;
+  ens_build_slots(e);
   e->args_ok = false;
   drop_egraph(e);
   return SGP_OK;

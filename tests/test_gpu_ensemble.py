@@ -32,7 +32,7 @@ def test_384_single_grid_radix3():
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
-@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("order", [2, 4, 6])
 def test_small_ensemble_batched_equals_unbatched_and_oracle(dtype, order):
     import torch
     from paper_2603_25282_amd.sgp import SGP_OPT_BATCHED, Solver

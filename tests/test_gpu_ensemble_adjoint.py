@@ -14,8 +14,8 @@ pytestmark = pytest.mark.gpu
 PIDX = [4, 3, 0, 1, 2]  # (gamma, Omega, c0, c1, c2) in the params tuple
 
 
-@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
-def test_ensemble_adjoint_equals_single_grid_adjoints(dtype):
+@pytest.mark.parametrize("dtype,order", [("complex128", 4), ("complex64", 4), ("complex128", 6)])
+def test_ensemble_adjoint_equals_single_grid_adjoints(dtype, order):
     import torch
     from paper_2603_25282_amd.autograd import ensemble_evolve, evolve
     from paper_2603_25282_amd.sgp import Ensemble, Solver
@@ -26,9 +26,9 @@ def test_ensemble_adjoint_equals_single_grid_adjoints(dtype):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(3)
     ws = [rng.standard_normal((5,) + c.shape) + 1j * rng.standard_normal((5,) + c.shape) for c in insts]
-    print(f"case ensemble adjoint {len(insts)} instances {dtype}", flush=True)
+    print(f"case ensemble adjoint {len(insts)} instances {dtype} TS{order}", flush=True)
     ens = Ensemble([c.shape for c in insts], [c.L for c in insts], [c.params for c in insts], dtype=dtype)
-    ens.build_propagator(tau, 4)
+    ens.build_propagator(tau, order)
     p0 = [torch.from_numpy(Solver.to_device_layout(I.initial_state(c))).to(tdt).to(dev).requires_grad_(True)
           for c in insts]
     par = torch.tensor([[c.params[i] for i in PIDX] for c in insts], dtype=torch.float64, requires_grad=True)
@@ -39,7 +39,7 @@ def test_ensemble_adjoint_equals_single_grid_adjoints(dtype):
     for k, c in enumerate(insts):
         q0 = torch.from_numpy(Solver.to_device_layout(I.initial_state(c))).to(tdt).to(dev).requires_grad_(True)
         qp = torch.tensor([c.params[i] for i in PIDX], dtype=torch.float64, requires_grad=True)
-        out = evolve(q0, qp, c.shape, c.L, c.params[5:8], tau, n, order=4, K=K)
+        out = evolve(q0, qp, c.shape, c.L, c.params[5:8], tau, n, order=order, K=K)
         g = torch.from_numpy(Solver.to_device_layout(ws[k])).to(tdt).to(dev)
         torch.sum((torch.conj(g) * out).real).backward()
         assert torch.equal(outs[k].detach(), out.detach()), f"instance {k} forward differs"
@@ -48,7 +48,7 @@ def test_ensemble_adjoint_equals_single_grid_adjoints(dtype):
     # one instance against the oracle's discrete adjoint
     k = 1
     c = insts[k]
-    g_ref, d_ref = oracle.adjoint(I.initial_state(c), ws[k], c.L, c.params, 4, tau, n, K=K)
+    g_ref, d_ref = oracle.adjoint(I.initial_state(c), ws[k], c.L, c.params, order, tau, n, K=K)
     g = Solver.from_device_layout(p0[k].grad.cpu().numpy().astype(np.complex128))
     eg = rel_l2(g, g_ref)
     ed = np.abs(par.grad[k].numpy() - d_ref) / np.maximum(1.0, np.abs(d_ref))
