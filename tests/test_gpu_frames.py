@@ -82,7 +82,10 @@ def test_lab_frame_algorithm1_matches_oracle(dtype, order):
         s.step_store(psi, 1, store)
 
 
-def test_lab_frame_3d_matches_oracle():
+@pytest.mark.parametrize("split", [0, 1])
+def test_lab_frame_3d_matches_oracle(split):
+    # both linear-substep splits (the propagator's spin part in the z-pass or in
+    # the forward y-pass) inside Algorithm 1's shears
     import torch
     from paper_2603_25282_amd.sgp import Solver
     base = I.with_(I.C3, shape=(16, 32, 32), L=6.0, name="lab3d")
@@ -93,12 +96,13 @@ def test_lab_frame_3d_matches_oracle():
     ref = oracle.evolve(psi0, cfg.L, cfg.params, 4, 2e-3, 4, frame="lab")
     s = Solver(cfg.shape, cfg.L, cfg.params, dtype="complex128")
     s.set_frame("lab")
+    s.set_plan([0, 0, 0, split])
     s.build_propagator(2e-3, 4)
     psi = to_gpu(s, psi0)
     s.step(psi, 4)
     torch.cuda.synchronize()
     err = rel_l2(Solver.from_device_layout(psi.cpu().numpy()), ref)
-    print("3D lab frame rel l2", err)
+    print(f"3D lab frame (split {split}) rel l2", err)
     assert err <= 1e-11
 
 
