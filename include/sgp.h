@@ -162,9 +162,15 @@ int sgp_jz_inner(sgp_ctx* ctx, const void* u_dev, const void* v_dev, double out[
  * adjacent component pairs: dM/dt = -2 gamma Im[Q1 + Q2 + sqrt6/2 (Q3 - Q4)] and
  * d<Lz>/dt = (gx^2 - gy^2) out[7] + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] with
  * Q1 = <psi_2, L_- psi_1>, Q2 = <psi_-1, L_- psi_-2>, Q3 = <psi_1, L_- psi_0>,
- * Q4 = <psi_-1, L_+ psi_0>, Q5 = <psi_1, L_+ psi_2>; all frame-invariant.
- * SGP_ERR_NONFINITE as sgp_observables.  Synchronous. */
-int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[11]);
+ * Q4 = <psi_-1, L_+ psi_0>, Q5 = <psi_1, L_+ psi_2>; all frame-invariant;
+ * out[11] = G(gamma, Psi), the spin-orbit term of Lemma 2's width law
+ * (d^2 delta_r/dt^2 = -4 gr^2 delta_r + 4 E(0) + 4 Omega <Lz> + G for a radial trap
+ * gx = gy = gr): 2 gamma Re h^d sum [Omega (i Y - X) F_+ + gamma (sum_m (6 - m^2)
+ * |psi_m|^2 + sum_m m conj(psi_m) L_z psi_m)] on the lab-frame state (for a
+ * rotating-frame state its lab-frame value: (X, Y) the lab-frame coordinates of the
+ * point and F_+ with the components' phase exp(-i Omega t) undone), L_z spectral.
+ * SGP_ERR_NONFINITE as sgp_observables.  Synchronous.  out holds 12 doubles. */
+int sgp_diagnostics(sgp_ctx* ctx, const void* psi_dev, double out[12]);
 
 /* ---- Differentiation (discrete adjoint of sgp_step) -------------------------
  * Convention: for a real loss J of the state, a gradient is g = 2 dJ/d conj(psi),

@@ -723,7 +723,7 @@ long pass_nblocks(const sgp_ctx* c, int axis, int e) {
 }
 
 template <typename T>
-int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
+int observables_impl(sgp_ctx* c, const void* psi, double out[12]) {
   double* part = (double*)c->at(c->off_part);
   double* red = (double*)c->at(c->off_red);
   double tot[3][NOBS];
@@ -786,6 +786,16 @@ int observables_impl(sgp_ctx* c, const void* psi, double out[11]) {
   out[9] = -2.0 * g * hd * (q1 + q2 + r6h * (q3 - q4)).imag();
   // out[10] = d<Lz>/dt = (gx^2 - gy^2) int x y rho + 2 gamma Im[Q2 - Q5 + sqrt6/2 (Q3 - Q4)] (Lemma 1)
   out[10] = (c->p.gx * c->p.gx - c->p.gy * c->p.gy) * out[7] + 2.0 * g * hd * (q2 - q5 + r6h * (q3 - q4)).imag();
+  // out[11] = G(gamma, Psi) of Lemma 2: 2 gamma Re int [Omega (i y - x) F_+ + gamma
+  // (sum_m (6 - m^2) |psi_m|^2 + sum_m m conj(psi_m) L_z psi_m)] on the lab-frame state.
+  // The rotating-frame state carries F_+ with the phase exp(i theta) of its
+  // components (theta = Omega s): F_+(lab, X) = exp(-i theta) F_+(x); the sums use
+  // the lab-frame coordinates (X, Y) of each point; the other two terms are
+  // frame-invariant
+  const double th = c->frame == SGP_FRAME_LAB ? 0.0 : c->p.Omega * c->t;
+  const cd A = c->p.Omega * std::exp(cd(0.0, -th)) * cd(tot[0][20], tot[0][21]);
+  const double B = tot[0][22], C = tot[0][23] + (c->g.dim >= 2 ? tot[1][12] : 0.0);
+  out[11] = 2.0 * g * hd * (A.real() + g * (B + C));
   // a NaN or infinity anywhere in the state reaches the mass sum (|psi|^2 over all
   // points) and every other sum
   for (int axis = 0; axis < c->g.dim; ++axis)
@@ -1187,7 +1197,7 @@ int sgp_rotation_map(sgp_ctx* c, void* psi, double t, int direction) {
 int sgp_observables(sgp_ctx* c, const void* psi, double out[4]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
-  double all[11];
+  double all[12];
   int rc = c->dtype == SGP_C64 ? observables_impl<float>(c, psi, all) : observables_impl<double>(c, psi, all);
   if (rc == SGP_OK || rc == SGP_ERR_NONFINITE) std::memcpy(out, all, 4 * sizeof(double));
   return rc;
@@ -1216,7 +1226,7 @@ int sgp_jz_inner(sgp_ctx* c, const void* u, const void* v, double out[2]) {
   return c->dtype == SGP_C64 ? jz_inner_impl<float>(c, u, v, out) : jz_inner_impl<double>(c, u, v, out);
 }
 
-int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[11]) {
+int sgp_diagnostics(sgp_ctx* c, const void* psi, double out[12]) {
   if (!c || !psi || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
   return c->dtype == SGP_C64 ? observables_impl<float>(c, psi, out) : observables_impl<double>(c, psi, out);

@@ -657,11 +657,13 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
       dr[cc] = lx[W * N * 5 + pt * 5 + cc].re;
       di[cc] = lx[W * N * 5 + pt * 5 + cc].im;
     }
-    double grad2 = 0.0, rot = 0.0;
+    double grad2 = 0.0, rot = 0.0, rotm = 0.0;
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
       grad2 += dr[cc] * dr[cc] + di[cc] * di[cc];
-      rot += pr[cc] * di[cc] - pi[cc] * dr[cc];  // Im(conj(psi) d psi)
+      const double r1 = pr[cc] * di[cc] - pi[cc] * dr[cc];  // Im(conj(psi) d psi)
+      rot += r1;
+      rotm += (2 - cc) * r1;  // weighted by m = 2 - cc (the F_z L_z density)
     }
     if constexpr (XL) {
       double n[5], rho = 0.0;
@@ -711,6 +713,13 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
       acc[17] += pr[1] * di[2] - pi[1] * dr[2];
       acc[18] += pr[3] * dr[2] + pi[3] * di[2];
       acc[19] += pr[3] * di[2] - pi[3] * dr[2];
+      // Lemma 2's spin-orbit term: (i Y - X) F_+ at the lab-frame point (real and
+      // imaginary parts), (f_x^2 + f_y^2) = 6 - m^2 weighted density, and the x-line
+      // part Re(conj(psi_m) i y d_x psi_m) of sum_m m conj(psi_m) L_z psi_m
+      acc[20] += -X * fr - Y * fi;
+      acc[21] += Y * fr - X * fi;
+      acc[22] += 2.0 * n[0] + 5.0 * n[1] + 6.0 * n[2] + 5.0 * n[3] + 2.0 * n[4];
+      acc[23] += -y * rotm;
     } else {
       acc[4] += 0.5 * grad2;
       if constexpr (KIND == OBS_Y) {
@@ -722,6 +731,7 @@ __global__ __launch_bounds__(W * 5 * (N / E)) void k_obs(const cx<T>* __restrict
           s += w[l] * ((pr[l] * di[l + 1] - pi[l] * dr[l + 1]) + (pr[l + 1] * di[l] - pi[l + 1] * dr[l]));
         acc[6] += -s;
         acc[11] += 2.0 * y * rot;
+        acc[12] += x * rotm;  // Re(conj(psi_m) (-i x) d_y psi_m), weighted by m
         // conj(psi_a) d_y psi_b for the same pairs
         acc[20] += pr[0] * dr[1] + pi[0] * di[1];
         acc[21] += pr[0] * di[1] - pi[0] * dr[1];

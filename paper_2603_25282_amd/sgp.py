@@ -225,11 +225,11 @@ class Solver:
         """sgp_diagnostics as a dict: mass, energy, magnetization, lz, delta_x,
         delta_y, delta_z, xy_rho, width_rate (= d delta_r/dt when gamma = 0),
         dM_dt and dLz_dt (the magnetization and angular-momentum laws, spin-orbit
-        terms included)."""
-        out = (ctypes.c_double * 11)()
+        terms included) and soc_width_term (G of Lemma 2's width law)."""
+        out = (ctypes.c_double * 12)()
         _check(lib().sgp_diagnostics(self._ctx, self._psi_ptr(psi), out), self._ctx)
         keys = ("mass", "energy", "magnetization", "lz", "delta_x", "delta_y", "delta_z", "xy_rho", "width_rate",
-                "dM_dt", "dLz_dt")
+                "dM_dt", "dLz_dt", "soc_width_term")
         return dict(zip(keys, out[:]))
 
     def time_pass(self, psi, pass_kind, reps, in_step=False, in_steps=False):

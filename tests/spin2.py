@@ -54,3 +54,31 @@ def nl_rhs(psi, params, V):
     rho, F, A00 = densities(psi)
     Ff = F[0] * FX + F[1] * FY + F[2] * FZ
     return -1j * ((V + c0 * rho) * psi + c1 * Ff @ psi + c2 * A00 * (AS @ np.conj(psi)))
+
+
+def soc_width_term(psi, L, params):
+    """G(gamma, Psi), the spin-orbit term of Lemma 2's width law (Sec. 2), written out
+    from its definition on a lab-frame 2D state (5, ny, nx) on [-L, L]^2:
+    2 gamma Re h^2 sum [Omega (i y - x) F_+ + gamma (2 rho + 3|psi_1|^2 + 4|psi_0|^2 +
+    3|psi_-1|^2 + sum_m m conj(psi_m) L_z psi_m)], F_+ = 2 (conj(psi_2) psi_1 +
+    conj(psi_-1) psi_-2) + sqrt6 (conj(psi_1) psi_0 + conj(psi_0) psi_-1),
+    L_z = -i (x d_y - y d_x) with spectral derivatives."""
+    ny, nx = psi.shape[1:]
+    h = 2.0 * L / nx
+    x = -L + h * np.arange(nx)
+    y = -L + (2.0 * L / ny) * np.arange(ny)
+    X, Y = np.meshgrid(x, y)
+    kx = np.pi * np.fft.fftfreq(nx, d=1.0 / nx) / L
+    ky = np.pi * np.fft.fftfreq(ny, d=1.0 / ny) / L
+    dx = np.fft.ifft(1j * kx[None, None, :] * np.fft.fft(psi, axis=-1), axis=-1)
+    dy = np.fft.ifft(1j * ky[None, :, None] * np.fft.fft(psi, axis=-2), axis=-2)
+    lz = -1j * (X[None] * dy - Y[None] * dx)
+    p = psi
+    fp = 2 * (np.conj(p[0]) * p[1] + np.conj(p[3]) * p[4]) + np.sqrt(6.0) * (np.conj(p[1]) * p[2] + np.conj(p[2]) * p[3])
+    n = np.abs(p) ** 2
+    rho = n.sum(axis=0)
+    m = np.array([2.0, 1.0, 0.0, -1.0, -2.0])[:, None, None]
+    Om, gam = params[3], params[4]
+    dens = Om * (1j * Y - X) * fp + gam * (2 * rho + 3 * n[1] + 4 * n[2] + 3 * n[3] +
+                                          np.sum(m * np.conj(p) * lz, axis=0))
+    return 2.0 * gam * np.real(h * (2.0 * L / ny) * np.sum(dens))

@@ -5,8 +5,10 @@ Example "dynamical laws" workload evolved on the GPU in FP64."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2603_25282_amd import inputs as I
 from tests.gpu_util import to_gpu
+from tests.spin2 import soc_width_term
 from tests.test_oracle_scheme import smooth_state, spectral_grad
 
 pytestmark = pytest.mark.gpu
@@ -55,8 +57,12 @@ def test_diagnostics_match_definitions(dtype):
     d = s.diagnostics(to_gpu(s, psi))
     dx, dy, xy, W = reference(psi, L, params[3] * t)
     dM, dLz = soc_rates(psi, L, params, xy)
-    got = np.array([d["delta_x"], d["delta_y"], d["xy_rho"], d["width_rate"], d["dM_dt"], d["dLz_dt"]])
-    ref = np.array([dx, dy, xy, W, dM, dLz])
+    # Lemma 2's spin-orbit term on the lab-frame state (psi is the rotating-frame state
+    # at clock t; the oracle's mapping takes it to the lab frame)
+    G = soc_width_term(oracle.rotation_map(psi, L, params, t, forward=False), L, params)
+    got = np.array([d["delta_x"], d["delta_y"], d["xy_rho"], d["width_rate"], d["dM_dt"], d["dLz_dt"],
+                    d["soc_width_term"]])
+    ref = np.array([dx, dy, xy, W, dM, dLz, G])
     print("gpu", got, "ref", ref, flush=True)
     tol = 1e-12 if dtype == "complex128" else 3e-6
     assert np.all(np.abs(got - ref) <= tol * np.maximum(1.0, np.abs(ref)))
@@ -167,6 +173,31 @@ def test_spin_orbit_laws_by_differences():
               f"law {law:.10e}", flush=True)
         assert abs(law) > 1e-3
         assert abs(fd - law) <= 1e-5 * abs(law)
+
+
+def test_width_law_with_spin_orbit_term():
+    # Lemma 2 with gamma = 0.9 on the dynamical-laws example's grid and a radial trap:
+    # the device's delta_x + delta_y, energy, <Lz> and spin-orbit term G(gamma, Psi)
+    # (sgp_diagnostics) satisfy d^2 delta_r/dt^2 = -4 delta_r + 4 E(0) + 4 Omega <Lz> + G,
+    # the second derivative by central differences of the same GPU trajectory (FP64,
+    # TS4, tau = 1e-3) at dt and dt/2, Richardson-extrapolated
+    p = list(I.EX3.params)
+    p[4], p[5], p[6] = 0.9, 1.0, 1.0
+    cfg = I.with_(I.EX3, params=tuple(p), name="ex3-soc-radial")
+    t0, dt = 0.5, 0.02
+    print("case width law with the spin-orbit term, 768^2 FP64", flush=True)
+    out = run_ex3(cfg, t0, t0, extra_times=(t0 - dt, t0 + dt, t0 - dt / 2, t0 + dt / 2))
+    m = lambda t: round(t / cfg.tau)
+    dr = lambda t: out[m(t)]["delta_x"] + out[m(t)]["delta_y"]
+    d2a = (dr(t0 + dt) - 2 * dr(t0) + dr(t0 - dt)) / dt ** 2
+    d2b = (dr(t0 + dt / 2) - 2 * dr(t0) + dr(t0 - dt / 2)) / (dt / 2) ** 2
+    d2 = (4 * d2b - d2a) / 3
+    o = out[m(t0)]
+    law = -4 * dr(t0) + 4 * out[0]["energy"] + 4 * cfg.params[3] * o["lz"] + o["soc_width_term"]
+    print(f"  d2 delta_r {d2a:.10e} (dt), {d2b:.10e} (dt/2), extrapolated {d2:.10e}; law {law:.10e} "
+          f"(G {o['soc_width_term']:.6e})", flush=True)
+    assert abs(o["soc_width_term"]) > 1e-2 * abs(law)
+    assert abs(d2 - law) <= 1e-6 * abs(law)
 
 
 def jz_reference(u, v, Ls):

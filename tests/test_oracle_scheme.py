@@ -1,6 +1,7 @@
 """Scheme-level pins for the oracle (Secs. 2, 3.3, 3.4): exact plane-wave evolution
 with the nonlinearity off, discrete mass and magnetization conservation, <Lz>
-conservation, the condensate-width closed form of Lemma 2, approximate energy
+conservation, the condensate-width closed form of Lemma 2 and its law with the
+spin-orbit term, approximate energy
 conservation, time reversibility, and equivalence of the rotating-frame evolution
 with the paper's literal lab-frame Algorithm 1 (RSDA mapping every step)."""
 import numpy as np
@@ -9,7 +10,7 @@ import scipy.linalg as sl
 
 import oracle
 from paper_2603_25282_amd import inputs as I
-from tests.spin2 import Qmat, Smat
+from tests.spin2 import Qmat, Smat, soc_width_term
 
 
 def spectral_grad(f, L):
@@ -151,6 +152,43 @@ def test_width_closed_form_without_soc():
     ref = (E + params[3] * lz) * (1 - np.cos(2 * t)) + d0 * np.cos(2 * t) + d1 / 2 * np.sin(2 * t)
     assert abs(dr - ref) < 1e-8 * abs(ref)
     assert abs(dr - d0) > 1e-2  # the width really moves
+
+
+def test_width_law_with_spin_orbit_term():
+    # Lemma 2 with gamma != 0 (radial trap gr = 1): d^2 delta_r/dt^2 = -4 delta_r + 4 E(0)
+    # + 4 Omega <Lz>(t) + G(gamma, Psi), G written out from its definition
+    # (tests.spin2.soc_width_term) on the lab-frame state; the second derivative of the
+    # oracle's delta_r(t) by central differences at dt and dt/2, Richardson-extrapolated.
+    # G's three parts (the Omega F_+ term, the weighted density, the F_z L_z term) are
+    # -5 %, 105 % and 0.2 % of it here, so dropping or mis-signing any one fails.
+    shape, L = (128, 128), 8.0
+    params = (10.0, 1.0, 1.0, 0.3, 0.5, 1.0, 1.0, 1.0)
+    X, Y = I.mesh(shape, L)
+    g = np.exp(-((X - 0.3) ** 2 + (Y + 0.2) ** 2) / 2.0)
+    psi0 = I.normalise(np.stack([g * (0.3 + 0.1j * X), g * (0.5 + 0.2 * Y), g * (1.0 + 0.1j * X * Y),
+                                 g * (0.4 - 0.1j * Y), g * 0.2 * (1 + 1j * X)]), shape, L)
+    h2 = (2 * L / shape[0]) ** 2
+    tau, n0, k = 1e-3, 100, 10
+    E0 = oracle.observables(psi0, L, params)[1]
+    states = {}
+    phi = oracle.evolve(psi0, L, params, 4, tau, n0 - 2 * k)
+    for j in range(-2, 3):
+        if j > -2:
+            phi = oracle.evolve(phi, L, params, 4, tau, k, t0=(n0 + (j - 1) * k) * tau)
+        states[j] = phi
+    t0 = n0 * tau
+    lab = {j: oracle.rotation_map(p, L, params, (n0 + j * k) * tau, forward=False) for j, p in states.items()}
+    dr = {j: h2 * np.sum((X ** 2 + Y ** 2) * np.abs(p) ** 2) for j, p in lab.items()}
+    dt = k * tau
+    d2a = (dr[2] - 2 * dr[0] + dr[-2]) / (2 * dt) ** 2
+    d2b = (dr[1] - 2 * dr[0] + dr[-1]) / dt ** 2
+    d2 = (4 * d2b - d2a) / 3
+    lz = oracle.observables(states[0], L, params, theta=params[3] * t0)[3]
+    G = soc_width_term(lab[0], L, params)
+    law = -4 * dr[0] + 4 * E0 + 4 * params[3] * lz + G
+    print(f"d2 delta_r: {d2a:.8f} (2 dt), {d2b:.8f} (dt), extrapolated {d2:.8f}; law {law:.8f} (G {G:.8f})")
+    assert abs(G) > 1.0
+    assert abs(d2 - law) <= 1e-7 * abs(law)
 
 
 @pytest.mark.parametrize("order", [2, 4])
