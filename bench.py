@@ -716,13 +716,14 @@ def cpu_model():
 
 
 def source_hash():
-    """Hash of the device-code sources (every kernel and what it includes; not the
-    host-side C ABI in sgp_api.hip): stored traffic counters apply only to them."""
+    """Hash of the pass kernels' device-code sources (every file they are compiled
+    from; not the host-side C ABI in sgp_api.hip nor the observables kernels in
+    sgp_obs.hpp): stored traffic counters apply only to them."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_25282_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")) and f != "sgp_api.hip":
+        if f.endswith((".hip", ".hpp")) and f not in ("sgp_api.hip", "sgp_obs.hpp"):
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 

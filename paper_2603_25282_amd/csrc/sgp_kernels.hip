@@ -1,8 +1,8 @@
 // Launch dispatch of the split-step kernels (the kernels themselves are in
-// sgp_passes.hpp): line length and register plan -> the instantiation compiled in
+// sgp_passes.hpp and, for the observables, sgp_obs.hpp): line length and register plan -> the instantiation compiled in
 // sgp_plan_inst.hip for that plan width; the batched ensemble passes; the
 // propagator tables.
-#include "sgp_passes.hpp"
+#include "sgp_obs.hpp"
 
 namespace sgp {
 

@@ -1,7 +1,7 @@
 // Instantiation of the pass and observables kernels of one (scalar type, register
 // plan width) pair; the build compiles this file once per pair with
 // -DSGP_INST_T=<float|double> -DSGP_INST_E=<4|8|12|16|24>.
-#include "sgp_passes.hpp"
+#include "sgp_obs.hpp"
 
 #if !defined(SGP_INST_T) || !defined(SGP_INST_E)
 #error "compile with -DSGP_INST_T=<float|double> -DSGP_INST_E=<plan width>"
