@@ -205,6 +205,11 @@ class Single:
         del psi
         if adjoint_steps > 0:
             out["fwd_adjoint"] = self.fwd_adjoint(adjoint_steps, K)
+            # one segment: the forward keeps every pass's stored input and the
+            # backward recomputes nothing, where that store fits a 16 GiB budget
+            if self.s.store_size(adjoint_steps) <= 16 << 30 and K < adjoint_steps:
+                out["fwd_adjoint_no_recompute"] = self.fwd_adjoint(adjoint_steps, adjoint_steps)
+                out["fwd_adjoint_no_recompute"]["store_GiB"] = self.s.store_size(adjoint_steps) / 2**30
         return out
 
     def fwd_adjoint(self, n_adj, K):
@@ -343,6 +348,8 @@ def main():
     }
     if "fwd_adjoint" in r:
         out["fwd_adjoint"] = r["fwd_adjoint"]
+    if "fwd_adjoint_no_recompute" in r:
+        out["fwd_adjoint_no_recompute"] = r["fwd_adjoint_no_recompute"]
 
     # the other element type of the same workload, and the metric's 3D shape in both
     others = []
