@@ -270,7 +270,14 @@ int sgp_autotune(sgp_ctx* ctx, void* psi_dev, int steps, int elems_out[3], doubl
 
 /* Options.  SGP_OPT_GRAPH (default 1): replay the periodic part of sgp_step()
  * from a captured HIP graph (value 0 launches every kernel individually). */
-enum { SGP_OPT_GRAPH = 1, SGP_OPT_BATCHED = 2, SGP_OPT_FRAME = 3 };
+enum { SGP_OPT_GRAPH = 1, SGP_OPT_BATCHED = 2, SGP_OPT_FRAME = 3, SGP_OPT_SLABS = 4 };
+/* SGP_OPT_SLABS (3D contexts; default 0 = off): S >= 2 z-slabs, S dividing nz.  With
+ * the graph replay and the linear-substep split 0, the passes of a step that act on
+ * each z-plane alone (the inverse y-pass, the x-pass, the next forward y-pass; Sec.
+ * 3.1's 3D step) run slab by slab between two z-passes, alternate slabs on a second
+ * stream, so that the bandwidth-bound y-passes of one slab overlap the x-pass of
+ * another.  Bitwise the same results.  SGP_ERR_ARG for a 2D context or an S that does
+ * not divide nz; 0 or 1 switches it off. */
 /* SGP_OPT_FRAME: SGP_FRAME_ROTATING (default) evolves Phi in the rotating frame
  * (trap at R(Omega s) x, merged nonlinear substeps, graph replay); SGP_FRAME_LAB runs
  * Algorithm 1 literally on the lab-frame Psi: nonlinear substeps with the trap at x

@@ -121,6 +121,11 @@ struct sgp_ctx {
   hipGraphExec_t gexec[kGraphLevels] = {};
   void* gpsi = nullptr;
   bool use_graph = true;
+  // 3D, split 0: the graph body runs its z-local passes (inverse y, X, forward y)
+  // per z-slab, the slabs alternating between two streams (0: off)
+  int slabs = 0;
+  hipStream_t cap2 = nullptr;
+  hipEvent_t pev[2] = {nullptr, nullptr};
 
   // measurement hook (sgp_time_pass with SGP_TIME_STEPS): while it is set, every
   // launch of pass `tev_pass` takes the next event pair of tev
@@ -410,6 +415,67 @@ hipError_t enqueue_body(sgp_ctx* c, hipStream_t st, void* psi, int nbody) {
   return hipSuccess;
 }
 
+// One z-local pass over the planes [z0, z1) of a 3D state: the x-pass (X_MID, the
+// clock on the device) or a y-pass transform (C_FWD / C_INV).  A z-slab is a
+// contiguous part of the state, so the pass runs on it as on a grid of z1 - z0
+// planes; only the x-pass's trap potential needs the planes' position (z0).
+template <typename T>
+hipError_t run_slab_pass(sgp_ctx* c, hipStream_t st, int kind, void* psi, int z0, int z1, double d) {
+  PassArgs a = base_args(c);
+  const int nx = c->g.n[0], ny = c->g.n[1];
+  void* p = (char*)psi + (size_t)z0 * ny * nx * 5 * 2 * c->esize;
+  a.d = d;
+  if (kind == X_MID) {
+    a.tw_fwd = c->at(c->off_tw[0][0]);
+    a.tw_inv = c->at(c->off_tw[0][1]);
+    a.clock_mode = CLOCK_DEVICE;
+    a.nlines = (long)(z1 - z0) * ny;
+    a.z0 = z0;
+    return launch_pass<T>(kind, p, a, nx, c->elems(0), st, nullptr);
+  }
+  column_geometry(c, 1, a);
+  a.nouter = z1 - z0;
+  return launch_pass<T>(kind, p, a, ny, c->elems(1), st, nullptr);
+}
+
+// enqueue_body with the z-local passes in z-slabs (3D, split 0): the inverse y-pass,
+// the x-pass and the next forward y-pass act on each z-plane alone, so between two
+// z-passes they run slab by slab, even slabs on st and odd ones on st2 (started one
+// inverse y-pass later), and the bandwidth-bound y-passes of one slab overlap the
+// VALU-bound x-pass of another.  The same kernels as enqueue_body on the same
+// lines: bitwise the same result.
+template <typename T>
+hipError_t enqueue_body_slabs(sgp_ctx* c, hipStream_t st, hipStream_t st2, void* psi, int nbody) {
+  std::vector<double> nl, lin;
+  std::vector<int> tab;
+  schedule(c, 2, nl, lin, tab);
+  const size_t per = lin.size() / 2;
+  const int S = c->slabs, dz = c->g.n[2] / S;
+  hipError_t e = run_colpass<T>(c, st, C_FWD, 1, psi, tab[per], lin[per]);
+  for (int b = 0; b < nbody && e == hipSuccess; ++b)
+    for (size_t k = per; k < 2 * per && e == hipSuccess; ++k) {
+      e = run_colpass<T>(c, st, C_PROP, 2, psi, tab[k], lin[k]);
+      const double d = (k + 1 == 2 * per) ? nl[per] : nl[k + 1];
+      const bool fwd_next = !(b + 1 == nbody && k + 1 == 2 * per);
+      for (int sl = 0; sl < S && e == hipSuccess; ++sl) {
+        hipStream_t q = (sl & 1) ? st2 : st;
+        const int z0 = sl * dz, z1 = z0 + dz;
+        e = run_slab_pass<T>(c, q, C_INV, psi, z0, z1, 0.0);
+        if (e == hipSuccess && sl == 0) {  // fork: st2 starts after the z-pass and slab 0's inverse y-pass
+          e = hipEventRecord(c->pev[0], st);
+          if (e == hipSuccess) e = hipStreamWaitEvent(st2, c->pev[0], 0);
+        }
+        if (e == hipSuccess) e = run_slab_pass<T>(c, q, X_MID, psi, z0, z1, d);
+        if (e == hipSuccess && fwd_next) e = run_slab_pass<T>(c, q, C_FWD, psi, z0, z1, 0.0);
+      }
+      if (e == hipSuccess) e = hipEventRecord(c->pev[1], st2);  // join
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, c->pev[1], 0);
+    }
+  return e;
+}
+
+bool slab_body(const sgp_ctx* c) { return c->slabs >= 2 && c->g.dim == 3 && c->lin_split == 0; }
+
 void drop_graph(sgp_ctx* c) {
   for (auto& g : c->gexec) {
     if (g) (void)hipGraphExecDestroy(g);
@@ -429,10 +495,18 @@ hipError_t get_graphs(sgp_ctx* c, void* psi) {
     e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
   }
+  const bool slabs = slab_body(c);
+  if (slabs && !c->cap2) {
+    e = hipStreamCreateWithFlags(&c->cap2, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      if (!c->pev[i]) e = hipEventCreateWithFlags(&c->pev[i], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
   for (int k = 0; k < sgp_ctx::kGraphLevels; ++k) {
     e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { drop_graph(c); return e; }
-    hipError_t e1 = enqueue_body<T>(c, c->cap, psi, 1 << k);
+    hipError_t e1 = slabs ? enqueue_body_slabs<T>(c, c->cap, c->cap2, psi, 1 << k)
+                          : enqueue_body<T>(c, c->cap, psi, 1 << k);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->cap, &g);
     if (e1 != hipSuccess || e != hipSuccess) {
@@ -1363,6 +1437,18 @@ int sgp_set_option(sgp_ctx* c, int option, long value) {
     drop_graph(c);
     return SGP_OK;
   }
+  if (option == SGP_OPT_SLABS) {
+    if (value == 0 || value == 1) {
+      c->slabs = 0;
+    } else {
+      if (c->g.dim != 3) return fail(c, SGP_ERR_ARG, "z-slabs need a 3D context");
+      if (value < 2 || value > c->g.n[2] || c->g.n[2] % value)
+        return fail(c, SGP_ERR_ARG, "the number of z-slabs must divide nz");
+      c->slabs = (int)value;
+    }
+    drop_graph(c);
+    return SGP_OK;
+  }
   return fail(c, SGP_ERR_ARG, "unknown option");
 }
 
@@ -1370,6 +1456,9 @@ void sgp_destroy(sgp_ctx* c) {
   if (!c) return;
   drop_graph(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->cap2) (void)hipStreamDestroy(c->cap2);
+  for (hipEvent_t ev : c->pev)
+    if (ev) (void)hipEventDestroy(ev);
   delete c;
 }
 

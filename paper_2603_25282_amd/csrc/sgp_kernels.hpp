@@ -27,8 +27,9 @@ enum { NOBS = 28 };  // partial sums per block of the observables kernels
 // x-line fields, column kinds (C_*) the column fields; both read the tables.
 struct PassArgs {
   // x-lines
-  long nlines;           // ny * nz
+  long nlines;           // ny * nz (a z-slab launch: ny * its planes)
   int ny;
+  int z0;                // first plane of a z-slab launch of an x-pass (trap's z coordinate)
   // columns (lines along y or z)
   long stride;           // element stride along the line (5 nx or 5 nx ny)
   long ncols;            // lines along the contiguous x axis (nx)

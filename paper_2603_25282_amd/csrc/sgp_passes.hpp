@@ -221,8 +221,10 @@ __device__ __forceinline__ void pass_body(cx<T>* __restrict__ psi, const PassArg
       double ct, st;
       trap_angle(a, ct, st);
       // (y, z) indices of the block's first line (uniform); the block's W lines follow it
-      const int iz0 = a.dim == 3 ? line0 / a.ny : 0;
-      const int iy0 = line0 - iz0 * a.ny;
+      // (z from the launch's first plane a.z0 on)
+      const int izl = a.dim == 3 ? line0 / a.ny : 0;
+      const int iy0 = line0 - izl * a.ny;
+      const int iz0 = izl + a.z0;
       for (int pt = tid; pt < W * N; pt += NT) {
         const int pc = pt / N, j = pt % N;
         const int line = (int)line0 + pc;  // y + ny z (< 2^31 for every supported grid)

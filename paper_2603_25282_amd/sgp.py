@@ -24,6 +24,7 @@ SGP_OPT_GRAPH, SGP_OPT_BATCHED = 1, 2
 SGP_TIME_IN_STEP = 256
 SGP_TIME_STEPS = 512
 SGP_OPT_FRAME = 3
+SGP_OPT_SLABS = 4
 SGP_FRAME_ROTATING, SGP_FRAME_LAB = 0, 1
 SGP_PLAN_LINEAR = 3
 
@@ -341,6 +342,11 @@ class Solver:
 
     def set_graph(self, on):
         _check(lib().sgp_set_option(self._ctx, 1, int(bool(on))), self._ctx)
+
+    def set_slabs(self, n):
+        """3D: run the z-local passes of the replayed step body in n z-slabs on two
+        streams (0 or 1: off; n must divide nz)."""
+        _check(lib().sgp_set_option(self._ctx, SGP_OPT_SLABS, int(n)), self._ctx)
 
     @property
     def time(self):

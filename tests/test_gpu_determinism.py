@@ -42,6 +42,40 @@ def test_steps_and_reductions_repeat_bitwise(shape, dtype):
     assert np.array_equal(oa, ob) and np.array_equal(da, db)
 
 
+@pytest.mark.parametrize("shape,dtype,slabs", [((32, 64, 32), "complex64", 4), ((32, 32, 64), "complex128", 2),
+                                               ((32, 16, 16), "complex64", 32)])
+def test_z_slab_body_is_bitwise_the_plain_body(shape, dtype, slabs):
+    # the pipelined graph body runs the same kernels on the same lines, in z-slabs on
+    # two streams: bitwise the same state (40 steps: graph replays of 1..32 steps)
+    import torch
+    print(f"case z-slabs {shape} {dtype} {slabs}", flush=True)
+    psi0 = _state(shape, 8.0, 43)
+    outs = []
+    for S in (0, slabs):
+        s = Solver(shape, 8.0, PARAMS, dtype=dtype)
+        s.build_propagator(1e-3, 4)
+        s.set_slabs(S)
+        psi = to_gpu(s, psi0)
+        s.step(psi, 40)
+        s.step(psi, 3)
+        torch.cuda.synchronize()
+        outs.append(psi)
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_z_slabs_rejected_where_they_do_not_fit():
+    from paper_2603_25282_amd.sgp import SgpError
+    s2 = Solver((32, 32), 8.0, PARAMS, dtype="complex64")
+    with pytest.raises(SgpError):
+        s2.set_slabs(2)
+    s3 = Solver((32, 32, 32), 8.0, PARAMS, dtype="complex64")
+    for bad in (3, 64, -2):
+        with pytest.raises(SgpError):
+            s3.set_slabs(bad)
+    s3.set_slabs(8)
+    s3.set_slabs(0)
+
+
 def test_adjoint_repeats_bitwise():
     import torch
     from paper_2603_25282_amd.autograd import evolve
