@@ -198,7 +198,8 @@ int sgp_step_store(sgp_ctx* ctx, void* psi_dev, long nsteps, void* store, size_t
 int sgp_adjoint_segment(sgp_ctx* ctx, void* lam_dev, long nsteps, const void* store, size_t store_bytes);
 
 /* Accumulated dJ/d(gamma, Omega, c0, c1, c2) of all sgp_adjoint_segment() calls since
- * the last reset; reset = 1 clears the accumulators.  Synchronous. */
+ * the last reset (the per-block slots summed on the device in a fixed order; five
+ * doubles come back); reset = 1 clears the accumulators.  Synchronous. */
 int sgp_adjoint_gradients(sgp_ctx* ctx, double out[5], int reset);
 
 /* Rotation clock t (the time of the rotating frame the state lives in). */

@@ -1375,18 +1375,16 @@ int sgp_adjoint_segment(sgp_ctx* c, void* lam, long nsteps, const void* store, s
 int sgp_adjoint_gradients(sgp_ctx* c, double out[5], int reset) {
   if (!c || !out) return fail(c, SGP_ERR_ARG, "null argument");
   if (!c->ws) return fail(c, SGP_ERR_STATE, "no workspace set");
-  std::vector<double> host((size_t)c->ngacc * NGRAD);
+  // the per-block slots summed on the device in a fixed order (the observables'
+  // reduction); only the NGRAD sums come back
   double* dev = (double*)c->at(c->off_gacc);
-  hipError_t e = hipMemcpyAsync(host.data(), dev, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->st);
+  double* sums = (double*)c->at(c->off_red);
+  hipError_t e = launch_sum_partials(dev, c->ngacc, NGRAD, sums, c->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, sums, sizeof(double) * NGRAD, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) return hip_fail(c, e, "gradient readback");
-  for (int q = 0; q < NGRAD; ++q) {
-    double acc = 0.0;
-    for (long b = 0; b < c->ngacc; ++b) acc += host[(size_t)b * NGRAD + q];
-    out[q] = acc;
-  }
+  if (e != hipSuccess) return hip_fail(c, e, "gradient reduction");
   if (reset) {
-    e = hipMemsetAsync(dev, 0, sizeof(double) * host.size(), c->st);
+    e = hipMemsetAsync(dev, 0, sizeof(double) * NGRAD * (size_t)c->ngacc, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) return hip_fail(c, e, "gradient reset");
   }
