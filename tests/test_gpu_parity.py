@@ -114,7 +114,7 @@ def test_observables_match_oracle(dtype, which):
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
-@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("order", [2, 4, 6])
 def test_3d_small_grids(dtype, order):
     # 3D passes (X, Y forward, Z with the propagator, Y inverse) on C3 physics at
     # reduced sizes, including an anisotropic in-plane trap so the rotation matters.
