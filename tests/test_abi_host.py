@@ -125,6 +125,16 @@ def test_plan_widths_and_plan_setters_without_device():
     assert L.sgp_get_plan(ctx, 3, ctypes.byref(e)) == 0 and e.value == 1
     assert L.sgp_set_plan(ctx, 3, 2) == -1 and b"split" in L.sgp_last_error(ctx)
     assert L.sgp_set_plan(ctx, 4, 0) == -1
+    # z-slabs of the pipelined step body (option 4): a divisor of nz (16 here), 0/1 = off
+    for S in (0, 1, 2, 4, 8, 16):
+        assert L.sgp_set_option(ctx, sgp.SGP_OPT_SLABS, S) == 0
+    for S in (3, 32, -2):
+        assert L.sgp_set_option(ctx, sgp.SGP_OPT_SLABS, S) == -1 and b"z-slabs" in L.sgp_last_error(ctx)
+    L.sgp_destroy(ctx)
+    rc, ctx = _create(n=(64, 64, 1))
+    assert rc == 0
+    assert L.sgp_set_option(ctx, sgp.SGP_OPT_SLABS, 2) == -1 and b"3D" in L.sgp_last_error(ctx)
+    assert L.sgp_set_option(ctx, sgp.SGP_OPT_SLABS, 0) == 0
     L.sgp_destroy(ctx)
 
 
